@@ -1,0 +1,167 @@
+"""Throughput of the fast-mode hot path on one MI355X.
+
+One step = the whole path on the 4096 x 4096-facet nadir workload (16.8M
+facets at 1 m, SWH 3 m, 128 gates x 256 Doppler bins, 65 spectra = 64 update
+intervals of 256 pulses, 16384 IQ pulses): for each spectrum the surface is
+synthesised and every facet rasterised (fused update+accumulate), then the
+spectra are inverse transformed, cross-faded and overlap-added into IQ.
+
+Prints one JSON line.  `value` is facet-updates/s of the FP32 context (range
+and phase in FP64); the plain FP64 context is reported beside it.  The
+spectrum is generated on the host once and is resident in HBM before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+METRIC = "facet-updates/s + simulated IQ pulses/s (FP32+FP64-phase vs FP64, same GPU)"
+
+# Algorithmic HBM bytes per facet and launch of each kernel (FP32 context;
+# FP64 doubles them): the column pass reads the spectrum once (8 B) and writes
+# six packed complex planes (48 B); the fused row pass reads the six planes
+# back (48 B) and writes nothing per facet.
+ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="track_4096")
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 context")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def timed_steps(sim, spec_t, wl, steps, warmup, torch):
+    T = sim.empty_spectra(wl.n_spec)
+    Y = torch.empty((wl.n_pulses, wl.radar.n_gates), dtype=sim.complex_dtype, device="cuda")
+
+    def step():
+        T.zero_()
+        sim.run(spec_t, wl.n_updates, t_fast=T, y=Y)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile(False)
+    return dt, prof, T, Y
+
+
+def roofline(prof, wl, bytes_scale):
+    """Dominant kernel against the HBM peak, from its event-timed launches."""
+    best = max((k for k in ALG_BYTES_PER_FACET), key=lambda k: prof[k][0])
+    ms, n = prof[best]
+    avg_s = ms / 1e3 / n
+    alg = ALG_BYTES_PER_FACET[best] * bytes_scale * wl.n_facets
+    achieved = alg / avg_s / 1e9
+    return {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+            "alg_bytes_per_launch": alg}
+
+
+def cpu_baseline(spec, wl):
+    """The oracle, as it stands, on one spectrum of the same workload."""
+    import oracle.fastmode as ofm
+    t0 = time.perf_counter()
+    ofm.doppler_spectrum(spec, wl.grid, wl.radar, wl.n_updates // 2)
+    dt = time.perf_counter() - t0
+    return {"value": round(wl.n_facets / dt, 1), "unit": "facet-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one spectrum (update {wl.n_updates // 2}) of the full {wl.grid.nx}x"
+                      f"{wl.grid.ny} workload, numpy float64, single thread, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2408_11472_amd import inputs, workloads, simradar
+
+    wl = workloads.ALL[a.workload]()
+    g = wl.grid
+    spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh, wl.sea.peak_wavelength,
+                               wl.sea.seed, wl.sea.swell)
+    results = {}
+    for name, prec, cdt, scale in (("fp32", simradar.SIM_PREC_FP32_PHASE64, np.complex64, 1),
+                                   ("fp64", simradar.SIM_PREC_FP64, np.complex128, 2)):
+        if name == "fp64" and a.no_fp64:
+            continue
+        sim = simradar.Simulator(g, wl.radar, prec)
+        spec_t = torch.as_tensor(spec.astype(cdt), device="cuda")
+        dt, prof, T, Y = timed_steps(sim, spec_t, wl, a.steps, a.warmup, torch)
+        ms_step = dt / a.steps * 1e3
+        results[name] = {
+            "ms_per_step": round(ms_step, 3),
+            "facet_updates_per_s": wl.n_facets * wl.n_spec * a.steps / dt,
+            "iq_pulses_per_s": wl.n_pulses * a.steps / dt,
+            "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items() if v[1]},
+            "roofline": roofline(prof, wl, scale),
+            "finite": bool(torch.isfinite(torch.view_as_real(Y)).all().item()),
+        }
+        print(f"[bench] {name}: {ms_step:.2f} ms/step  "
+              f"{results[name]['facet_updates_per_s']:.3e} facet-updates/s  "
+              f"kernels {results[name]['kernels_ms_per_step']}", file=sys.stderr, flush=True)
+        del T, Y, spec_t
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    r32 = results["fp32"]
+    line = {
+        "metric": METRIC,
+        "value": round(r32["facet_updates_per_s"], 1),
+        "unit": "facet-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "facets": wl.n_facets, "spectra": wl.n_spec,
+                   "n_gates": wl.radar.n_gates, "n_doppler": wl.radar.n_doppler,
+                   "n_fast": wl.radar.n_fast, "pulses": wl.n_pulses,
+                   "range_phase": "f64", "parallelism": "single-gpu"},
+        "iq_pulses_per_s": round(r32["iq_pulses_per_s"], 1),
+        "kernels_ms_per_step": r32["kernels_ms_per_step"],
+        "roofline": r32["roofline"],
+    }
+    if "fp64" in results:
+        r64 = results["fp64"]
+        line["fp64"] = {"value": round(r64["facet_updates_per_s"], 1),
+                        "iq_pulses_per_s": round(r64["iq_pulses_per_s"], 1),
+                        "ms_per_step": r64["ms_per_step"],
+                        "kernels_ms_per_step": r64["kernels_ms_per_step"],
+                        "roofline": r64["roofline"]}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec, wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,10 +67,18 @@ def multipliers(grid):
 
 
 def evolved(spec0, grid, t):
-    """c(k) exp(-i w(k) t) with the deep-water dispersion relation."""
+    """c(k) exp(-i w(k) t) with the deep-water dispersion relation.
+
+    The zero mode and the Nyquist row and column carry no wave (the input
+    convention of the coefficients; the generator never fills them), so they
+    are cleared here."""
     KX, KY = wavenumbers(grid)
     w = np.sqrt(grid.gravity * np.hypot(KX, KY))
-    return spec0 * np.exp(-1j * w * t)
+    c = np.array(spec0, dtype=complex)
+    c[0, 0] = 0.0
+    c[grid.ny // 2, :] = 0.0
+    c[:, grid.nx // 2] = 0.0
+    return c * np.exp(-1j * w * t)
 
 
 def fields(spec0, grid, t, names=FIELDS):
@@ -78,7 +86,7 @@ def fields(spec0, grid, t, names=FIELDS):
 
     numpy's ifft2 carries a 1/(nx ny) factor and the + sign in the exponent,
     so the modal sum is ifft2(.) * nx * ny."""
-    c = evolved(np.asarray(spec0, dtype=complex), grid, t)
+    c = evolved(spec0, grid, t)
     m = multipliers(grid)
     scale = grid.nx * grid.ny
     return {n: np.real(np.fft.ifft2(m[n] * c)) * scale for n in names}

@@ -1,0 +1,588 @@
+// C ABI of the fast-mode simulator (include/simradar.h): validation, launch
+// plans, workspace layout and the calls that chain the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/simradar.h"
+#include "launch.hpp"
+
+using simk::ColPlan;
+using simk::GridP;
+using simk::RadarP;
+using simk::RowPlan;
+using simk::WinP;
+
+struct sim_ctx {
+  int device;
+  sim_precision prec;
+  void* tw;            // kTwSize complex, precision of the context
+  void* ws;
+  size_t ws_bytes;
+  // per-kernel timing
+  bool profiling;
+  std::vector<hipEvent_t> ev;   // pool, pairs (start, stop)
+  std::vector<int> kind;        // kernel kind of each recorded pair
+  size_t used;                  // pairs recorded
+};
+
+namespace {
+
+constexpr size_t kLdsBudget = 159 * 1024;      // usable LDS per block
+constexpr size_t kWindowBudget = 32 * 1024;    // LDS of one window of partial spectra
+constexpr int kSlots = 4;                      // window slots per band
+constexpr int kMaxBands = 512;
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(long v) {
+  int r = 0;
+  while ((1L << r) < v) ++r;
+  return r;
+}
+long floor_pow2(long v) {
+  long r = 1;
+  while ((r << 1) <= v) r <<= 1;
+  return r;
+}
+size_t lpad(size_t i) { return i + (i >> 4); }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+bool isfin(double v) { return std::isfinite(v); }
+
+size_t csize(const sim_ctx* c) { return c->prec == SIM_PREC_FP64 ? 16 : 8; }
+
+sim_status check_grid(const sim_ctx* c, const sim_grid* g) {
+  if (!g) return SIM_ERR_ARG;
+  if (!is_pow2(g->nx) || !is_pow2(g->ny)) return SIM_ERR_UNSUPPORTED;
+  if (g->nx < 16 || g->nx > 4096 || g->ny < 16 || g->ny > 8192) return SIM_ERR_UNSUPPORTED;
+  if (!(isfin(g->dx) && g->dx > 0 && isfin(g->dy) && g->dy > 0)) return SIM_ERR_ARG;
+  if (!(isfin(g->x_origin) && isfin(g->y_origin))) return SIM_ERR_ARG;
+  if (!(isfin(g->gravity) && g->gravity > 0)) return SIM_ERR_ARG;
+  return SIM_OK;
+}
+
+sim_status check_radar(const sim_radar* r) {
+  if (!r) return SIM_ERR_ARG;
+  if (!(isfin(r->altitude) && r->altitude > 0 && isfin(r->velocity) && isfin(r->sat_x) &&
+        isfin(r->sat_y0) && isfin(r->carrier_hz) && r->carrier_hz > 0 && isfin(r->prf_hz) &&
+        r->prf_hz > 0 && isfin(r->gate_spacing) && r->gate_spacing > 0 &&
+        isfin(r->window_start) && isfin(r->beamwidth_3db) && r->beamwidth_3db > 0 &&
+        isfin(r->fresnel_sq) && r->fresnel_sq >= 0 && isfin(r->mss) && r->mss > 0))
+    return SIM_ERR_ARG;
+  if (r->n_gates < 1 || r->n_fast < 1) return SIM_ERR_ARG;
+  if (r->window != SIM_WIN_SQRT_TRIANGLE && r->window != SIM_WIN_SQRT_RAISED_COSINE)
+    return SIM_ERR_ARG;
+  if (!is_pow2(r->n_doppler) || r->n_doppler < 2 || r->n_doppler > 2048)
+    return SIM_ERR_UNSUPPORTED;
+  if (r->n_gates > 65536) return SIM_ERR_UNSUPPORTED;
+  return SIM_OK;
+}
+
+ColPlan col_plan(int nx, int ny, size_t cs) {
+  ColPlan p;
+  const int tps = ny / 16;
+  int cpb = 16;
+  while (cpb > 1 && ((long)cpb * tps > 512 || (size_t)cpb * lpad(ny) * cs > kLdsBudget)) cpb >>= 1;
+  if (cpb > nx) cpb = nx;
+  p.cpb = cpb;
+  p.threads = cpb * tps;
+  p.lds_bytes = (size_t)cpb * lpad(ny) * cs;
+  return p;
+}
+
+// Bins per window: the whole spectrum when it fits, else the largest power
+// of two that fits the window budget and what the row transforms leave.
+int window_bins(int G, int N, size_t cs, size_t fft_bytes) {
+  size_t budget = kWindowBudget;
+  const size_t left = kLdsBudget > fft_bytes + 512 ? kLdsBudget - fft_bytes - 512 : 0;
+  if (left < budget) budget = left;
+  const size_t per_bin = (size_t)G * cs;
+  if (per_bin == 0 || budget < per_bin) return 0;
+  const long wk = floor_pow2((long)(budget / per_bin));
+  return wk >= N ? N : (int)wk;
+}
+
+RowPlan row_plan(int nx, size_t cs) {
+  RowPlan p;
+  const int tpr = nx / 8;
+  p.rpb = tpr >= 256 ? 1 : 256 / tpr;
+  p.threads = p.rpb * tpr;
+  p.fft_bytes = (size_t)p.rpb * lpad(nx) * cs;
+  p.acc_bytes = 0;
+  return p;
+}
+
+struct WsLayout {
+  size_t planes, part, hdr, bandcnt, total;
+};
+
+WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
+  WsLayout L;
+  const size_t P = (size_t)g->nx * g->ny;
+  const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
+  size_t off = 0;
+  L.planes = off;
+  off = align256(off + 6 * P * cs);
+  L.part = off;
+  off = align256(off + (size_t)kMaxBands * kSlots * r->n_gates * (size_t)(wk > 0 ? wk : 1) * cs);
+  L.hdr = off;
+  off = align256(off + (size_t)kMaxBands * kSlots * 16);
+  L.bandcnt = off;
+  off = align256(off + (size_t)kMaxBands * 8 * 4);
+  L.total = off;
+  return L;
+}
+
+void fill_grid(const sim_grid* g, GridP& gp) {
+  gp.nx = g->nx;
+  gp.ny = g->ny;
+  gp.log2nx = ilog2(g->nx);
+  gp.log2ny = ilog2(g->ny);
+  gp.cwm = g->cwm ? 1 : 0;
+  gp.dx = g->dx;
+  gp.dy = g->dy;
+  gp.x_origin = g->x_origin;
+  gp.y_origin = g->y_origin;
+  gp.gravity = g->gravity;
+}
+
+// Platform positions, Doppler constant and amplitude constants.  The double
+// expressions below are the ones the range and index arithmetic is defined
+// with (evaluated once here, in this order).
+void fill_radar(const sim_radar* r, const sim_grid* g, double t, RadarP& rp) {
+  rp.altitude = r->altitude;
+  rp.sat_x = r->sat_x;
+  rp.sat_y1 = r->sat_y0 + r->velocity * t;
+  const double t2 = t + 1.0 / r->prf_hz;
+  rp.sat_y2 = r->sat_y0 + r->velocity * t2;
+  rp.k2 = 2.0 * r->carrier_hz / 299792458.0;
+  rp.gate_spacing = r->gate_spacing;
+  rp.window_start = r->window_start;
+  rp.fresnel_over_mss = r->fresnel_sq / r->mss;
+  rp.inv_mss = 1.0 / r->mss;
+  const double sh = std::sin(0.5 * r->beamwidth_3db);
+  const double gamma = (2.0 / std::log(2.0)) * sh * sh;
+  rp.two_over_gamma = 2.0 / gamma;
+  rp.cell_area = g->dx * g->dy;
+  rp.G = r->n_gates;
+  rp.N = r->n_doppler;
+  rp.log2N = ilog2(r->n_doppler);
+}
+
+sim_status use_device(const sim_ctx* c) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return SIM_ERR_DEVICE;
+  if (cur != c->device && hipSetDevice(c->device) != hipSuccess) return SIM_ERR_DEVICE;
+  return SIM_OK;
+}
+
+// SIMRADAR_DEBUG=1 prints the HIP error behind every SIM_ERR_DEVICE.
+sim_status dev_err(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SIM_OK;
+  const char* dbg = std::getenv("SIMRADAR_DEBUG");
+  if (dbg && dbg[0] == '1')
+    std::fprintf(stderr, "simradar: %s: %s (%d)\n", what, hipGetErrorString(e), (int)e);
+  return SIM_ERR_DEVICE;
+}
+#define dev(e) dev_err((e), #e)
+
+template <typename Real>
+void make_twiddles(Real* host) {
+  const long double two_pi = 6.283185307179586476925286766559L;
+  for (int m = 0; m < simk::kTwSize; ++m) {
+    const long double a = two_pi * (long double)m / (long double)simk::kTwSize;
+    host[2 * m] = (Real)cosl(a);
+    host[2 * m + 1] = (Real)sinl(a);
+  }
+}
+
+bool facets_ok(const sim_facets* f) {
+  if (!f) return false;
+  void* const p[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
+                      f->dh};
+  for (void* q : p)
+    if (!q) return false;
+  return true;
+}
+
+WinP win_params(sim_ctx* c, const sim_radar* r, const WsLayout& L, int wk, int n_bands,
+                int band_size) {
+  WinP wp;
+  char* base = (char*)c->ws;
+  wp.WK = wk;
+  wp.log2WK = ilog2(wk);
+  wp.S = kSlots;
+  wp.n_bands = n_bands;
+  wp.band_rows = band_size;
+  wp.part = base + L.part;
+  wp.hdr = (int4*)(base + L.hdr);
+  wp.bandcnt = (uint32_t*)(base + L.bandcnt);
+  (void)r;
+  return wp;
+}
+
+sim_status common_checks(sim_ctx* c, const sim_grid* g, const sim_radar* r, WsLayout* L) {
+  if (!c) return SIM_ERR_ARG;
+  sim_status s = check_grid(c, g);
+  if (s != SIM_OK) return s;
+  if (r) {
+    s = check_radar(r);
+    if (s != SIM_OK) return s;
+  }
+  if (!c->ws) return SIM_ERR_WORKSPACE;
+  if (r) {
+    *L = ws_layout(g, r, csize(c));
+    if (L->total > c->ws_bytes) return SIM_ERR_WORKSPACE;
+  } else {
+    const size_t need = align256(6 * (size_t)g->nx * g->ny * csize(c));
+    if (need > c->ws_bytes) return SIM_ERR_WORKSPACE;
+    L->planes = 0;
+  }
+  return SIM_OK;
+}
+
+// Bracket one kernel launch with events when profiling is on.
+struct ProfScope {
+  sim_ctx* c;
+  hipStream_t st;
+  bool on;
+  ProfScope(sim_ctx* c_, int kind, hipStream_t st_) : c(c_), st(st_), on(c_->profiling) {
+    if (!on) return;
+    if (c->used * 2 + 2 > c->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        on = false;
+        return;
+      }
+      c->ev.push_back(a);
+      c->ev.push_back(b);
+      c->kind.push_back(0);
+    }
+    c->kind[c->used] = kind;
+    (void)hipEventRecord(c->ev[2 * c->used], st);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(c->ev[2 * c->used + 1], st);
+    c->used++;
+  }
+};
+
+template <typename Real>
+sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, const sim_radar* r,
+                            double t, int32_t j, void* t_fast, sim_counters* counters,
+                            int32_t* code, hipStream_t st, const WsLayout& L) {
+  GridP gp;
+  RadarP rp;
+  fill_grid(g, gp);
+  fill_radar(r, g, t, rp);
+  const size_t cs = sizeof(Real) * 2;
+  char* base = (char*)c->ws;
+  void* planes = base + L.planes;
+  const ColPlan cp = col_plan(g->nx, g->ny, cs);
+  if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
+  RowPlan rpl = row_plan(g->nx, cs);
+  const int wk = window_bins(r->n_gates, r->n_doppler, cs, rpl.fft_bytes);
+  if (wk < 1) return SIM_ERR_UNSUPPORTED;
+  rpl.acc_bytes = rpl.fft_bytes + (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
+  const int target = rpl.threads <= 512 ? kMaxBands : kMaxBands / 2;
+  int n_bands, band_rows;
+  if (g->ny >= rpl.rpb) {
+    n_bands = g->ny / rpl.rpb < target ? g->ny / rpl.rpb : target;
+    band_rows = g->ny / n_bands;
+  } else {
+    n_bands = 1;
+    band_rows = rpl.rpb;
+  }
+  const WinP wp = win_params(c, r, L, wk, n_bands, band_rows);
+  void* Tj = (char*)t_fast + (size_t)j * r->n_gates * r->n_doppler * cs;
+  sim_status s;
+  {
+    ProfScope p(c, SIM_KERNEL_SURFACE_COLPASS, st);
+    s = dev(simk::launch_colpass<Real>(spec0, planes, gp, t, 1.0 / r->prf_hz, cp, c->tw, st));
+  }
+  if (s != SIM_OK) return s;
+  {
+    ProfScope p(c, SIM_KERNEL_FUSED_ROWPASS, st);
+    s = dev(simk::launch_rowpass_accumulate<Real>(planes, gp, rp, wp, Tj, code, rpl, c->tw, st));
+  }
+  if (s != SIM_OK) return s;
+  ProfScope p(c, SIM_KERNEL_REDUCE_PARTIALS, st);
+  return dev(simk::launch_reduce<Real>(rp, wp, Tj, (unsigned long long*)counters, st));
+}
+
+template <typename Real>
+sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
+                             const sim_radar* r, double t, int32_t j, void* t_fast,
+                             sim_counters* counters, int32_t* code, hipStream_t st,
+                             const WsLayout& L) {
+  GridP gp;
+  RadarP rp;
+  fill_grid(g, gp);
+  fill_radar(r, g, t, rp);
+  const size_t cs = sizeof(Real) * 2;
+  const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
+  if (wk < 1) return SIM_ERR_UNSUPPORTED;
+  const size_t P = (size_t)g->nx * g->ny;
+  size_t band = P / kMaxBands;
+  if (band < 1024) band = 1024;
+  const int n_bands = (int)((P + band - 1) / band);
+  const WinP wp = win_params(c, r, L, wk, n_bands, (int)band);
+  const size_t lds = (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
+  void* const fp[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
+                       f->dh};
+  void* Tj = (char*)t_fast + (size_t)j * r->n_gates * r->n_doppler * cs;
+  sim_status s;
+  {
+    ProfScope p(c, SIM_KERNEL_ACCUMULATE_FACETS, st);
+    s = dev(simk::launch_accumulate_facets<Real>(fp, gp, rp, wp, Tj, code, lds, st));
+  }
+  if (s != SIM_OK) return s;
+  ProfScope p(c, SIM_KERNEL_REDUCE_PARTIALS, st);
+  return dev(simk::launch_reduce<Real>(rp, wp, Tj, (unsigned long long*)counters, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_abi_version(void) { return SIM_ABI_VERSION; }
+
+const char* sim_status_string(sim_status s) {
+  switch (s) {
+    case SIM_OK: return "ok";
+    case SIM_ERR_ARG: return "invalid argument";
+    case SIM_ERR_SHAPE: return "inconsistent shape or index";
+    case SIM_ERR_UNSUPPORTED: return "unsupported size";
+    case SIM_ERR_WORKSPACE: return "workspace missing or too small";
+    case SIM_ERR_DEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
+  if (!ctx) return SIM_ERR_ARG;
+  *ctx = nullptr;
+  if (precision != SIM_PREC_FP64 && precision != SIM_PREC_FP32_PHASE64) return SIM_ERR_ARG;
+  int n = 0;
+  if (dev(hipGetDeviceCount(&n)) != SIM_OK) return SIM_ERR_DEVICE;
+  if (device < 0 || device >= n) return SIM_ERR_ARG;
+  if (dev(hipSetDevice(device)) != SIM_OK) return SIM_ERR_DEVICE;
+  int lds_max = 0;
+  if (dev(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device)) !=
+      SIM_OK)
+    return SIM_ERR_DEVICE;
+  if ((size_t)lds_max < kLdsBudget) {
+    dev_err(hipErrorInvalidValue, "device LDS per block below the 159 KiB the kernels plan for");
+    return SIM_ERR_UNSUPPORTED;
+  }
+  // the attribute only raises the dynamic-LDS cap; a runtime that does not
+  // need it may refuse it, which is harmless
+  if (simk::init_kernel_attributes(lds_max) != hipSuccess) (void)hipGetLastError();
+  sim_ctx* c = new (std::nothrow) sim_ctx;
+  if (!c) return SIM_ERR_DEVICE;
+  c->device = device;
+  c->prec = precision;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->tw = nullptr;
+  c->profiling = false;
+  c->used = 0;
+  const size_t cs = csize(c);
+  const size_t bytes = (size_t)simk::kTwSize * cs;
+  if (dev(hipMalloc(&c->tw, bytes)) != SIM_OK) {
+    delete c;
+    return SIM_ERR_DEVICE;
+  }
+  char* host = new (std::nothrow) char[bytes];
+  if (!host) {
+    (void)hipFree(c->tw);
+    delete c;
+    return SIM_ERR_DEVICE;
+  }
+  if (precision == SIM_PREC_FP64)
+    make_twiddles<double>((double*)host);
+  else
+    make_twiddles<float>((float*)host);
+  const sim_status e = dev(hipMemcpy(c->tw, host, bytes, hipMemcpyHostToDevice));
+  delete[] host;
+  if (e != SIM_OK) {
+    (void)hipFree(c->tw);
+    delete c;
+    return SIM_ERR_DEVICE;
+  }
+  *ctx = c;
+  return SIM_OK;
+}
+
+sim_status sim_destroy(sim_ctx* ctx) {
+  if (!ctx) return SIM_OK;
+  sim_status s = SIM_OK;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->tw) {
+    if (use_device(ctx) != SIM_OK || hipFree(ctx->tw) != hipSuccess) s = SIM_ERR_DEVICE;
+  }
+  delete ctx;
+  return s;
+}
+
+sim_status sim_get_precision(const sim_ctx* ctx, sim_precision* precision) {
+  if (!ctx || !precision) return SIM_ERR_ARG;
+  *precision = ctx->prec;
+  return SIM_OK;
+}
+
+sim_status sim_workspace_size(const sim_ctx* ctx, const sim_grid* grid, const sim_radar* radar,
+                              size_t* bytes) {
+  if (!ctx || !bytes) return SIM_ERR_ARG;
+  sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (window_bins(radar->n_gates, radar->n_doppler, csize(ctx), 0) < 1) return SIM_ERR_UNSUPPORTED;
+  *bytes = ws_layout(grid, radar, csize(ctx)).total;
+  return SIM_OK;
+}
+
+sim_status sim_set_workspace(sim_ctx* ctx, void* device_ptr, size_t bytes) {
+  if (!ctx) return SIM_ERR_ARG;
+  if (bytes == 0) {
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    return SIM_OK;
+  }
+  if (!device_ptr || ((uintptr_t)device_ptr & 255) != 0) return SIM_ERR_ARG;
+  ctx->ws = device_ptr;
+  ctx->ws_bytes = bytes;
+  return SIM_OK;
+}
+
+sim_status sim_surface_update(sim_ctx* ctx, const sim_grid* grid, const void* spec0, double t,
+                              double dt_pair, const sim_facets* out, void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, nullptr, &L);
+  if (s != SIM_OK) return s;
+  if (!spec0 || !facets_ok(out) || !isfin(t) || !isfin(dt_pair)) return SIM_ERR_ARG;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  GridP gp;
+  fill_grid(grid, gp);
+  const size_t cs = csize(ctx);
+  const ColPlan cp = col_plan(grid->nx, grid->ny, cs);
+  if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
+  const RowPlan rpl = row_plan(grid->nx, cs);
+  void* const o[9] = {out->disp_x, out->disp_y, out->h, out->sx, out->sy, out->jac,
+                      out->ddisp_x, out->ddisp_y, out->dh};
+  hipStream_t st = (hipStream_t)stream;
+  void* planes = ctx->ws;
+  const bool f64 = ctx->prec == SIM_PREC_FP64;
+  {
+    ProfScope p(ctx, SIM_KERNEL_SURFACE_COLPASS, st);
+    s = f64 ? dev(simk::launch_colpass<double>(spec0, planes, gp, t, dt_pair, cp, ctx->tw, st))
+            : dev(simk::launch_colpass<float>(spec0, planes, gp, t, dt_pair, cp, ctx->tw, st));
+  }
+  if (s != SIM_OK) return s;
+  ProfScope p(ctx, SIM_KERNEL_SURFACE_ROWPASS, st);
+  return f64 ? dev(simk::launch_rowpass_facets<double>(planes, gp, o, rpl, ctx->tw, st))
+             : dev(simk::launch_rowpass_facets<float>(planes, gp, o, rpl, ctx->tw, st));
+}
+
+sim_status sim_range_doppler_accumulate(sim_ctx* ctx, const sim_grid* grid,
+                                        const sim_facets* facets, const sim_radar* radar,
+                                        double t, int32_t j, void* t_fast, int32_t n_spec,
+                                        sim_counters* counters, int32_t* facet_code,
+                                        void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, radar, &L);
+  if (s != SIM_OK) return s;
+  if (!facets_ok(facets) || !t_fast || !isfin(t)) return SIM_ERR_ARG;
+  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->prec == SIM_PREC_FP64)
+    return accumulate_facets<double>(ctx, grid, facets, radar, t, j, t_fast, counters, facet_code,
+                                     st, L);
+  return accumulate_facets<float>(ctx, grid, facets, radar, t, j, t_fast, counters, facet_code,
+                                  st, L);
+}
+
+sim_status sim_update_and_accumulate(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
+                                     const sim_radar* radar, double t, int32_t j, void* t_fast,
+                                     int32_t n_spec, sim_counters* counters,
+                                     int32_t* facet_code, void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, radar, &L);
+  if (s != SIM_OK) return s;
+  if (!spec0 || !t_fast || !isfin(t)) return SIM_ERR_ARG;
+  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->prec == SIM_PREC_FP64)
+    return accumulate_fused<double>(ctx, grid, spec0, radar, t, j, t_fast, counters, facet_code,
+                                    st, L);
+  return accumulate_fused<float>(ctx, grid, spec0, radar, t, j, t_fast, counters, facet_code, st,
+                                 L);
+}
+
+sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* t_fast,
+                              int32_t n_spec, void* y, void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!t_fast || !y) return SIM_ERR_ARG;
+  if (n_spec < 2) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  const size_t cs = csize(ctx);
+  const int N = radar->n_doppler;
+  long gb = (long)(kLdsBudget / (4 * (size_t)N * cs));
+  if (gb < 1) return SIM_ERR_UNSUPPORTED;
+  if (gb > 64) gb = 64;
+  if (gb > radar->n_gates) gb = radar->n_gates;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope p(ctx, SIM_KERNEL_SEGMENTS_TO_IQ, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_segments_to_iq<double>(t_fast, y, radar->n_gates, N, ilog2(N),
+                                                   radar->n_fast, radar->window, n_spec - 1,
+                                                   (int)gb, ctx->tw, st));
+  return dev(simk::launch_segments_to_iq<float>(t_fast, y, radar->n_gates, N, ilog2(N),
+                                                radar->n_fast, radar->window, n_spec - 1, (int)gb,
+                                                ctx->tw, st));
+}
+
+sim_status sim_profile_enable(sim_ctx* ctx, int enable) {
+  if (!ctx) return SIM_ERR_ARG;
+  ctx->profiling = enable != 0;
+  if (enable) ctx->used = 0;
+  return SIM_OK;
+}
+
+sim_status sim_profile_read(sim_ctx* ctx, sim_kernel_times* out) {
+  if (!ctx || !out) return SIM_ERR_ARG;
+  for (int k = 0; k < SIM_KERNEL_KINDS; ++k) {
+    out->ms[k] = 0.0;
+    out->launches[k] = 0;
+  }
+  if (ctx->used == 0) return SIM_OK;
+  sim_status s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  for (size_t i = 0; i < ctx->used; ++i) {
+    s = dev(hipEventSynchronize(ctx->ev[2 * i + 1]));
+    if (s != SIM_OK) return s;
+    float ms = 0.f;
+    s = dev(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+    if (s != SIM_OK) return s;
+    out->ms[ctx->kind[i]] += (double)ms;
+    out->launches[ctx->kind[i]] += 1;
+  }
+  return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,579 @@
+// HIP kernels of the fast-mode hot path for gfx950, with their host launch
+// wrappers (called by the C ABI in api.cpp).
+//
+//   colpass              spectrum evolution + Hermitian packing of the 11 real
+//                        surface fields into 6 complex spectra, inverse FFT
+//                        along y (Sec. II.A surface synthesis, first half)
+//   rowpass_facets       inverse FFT along x, facet geometry, facet SoA out
+//   rowpass_accumulate   inverse FFT along x, facet geometry, scatterers and
+//                        rasterisation into LDS windows (Algorithm 1), fused
+//   accumulate_facets    scatterers and rasterisation from a facet SoA
+//   reduce_partials      ordered sum of the band windows into T_fast[j]
+//   segments_to_iq       per-gate inverse FFT, eq. (1) weights, overlap-add
+#include "device_common.hpp"
+#include "scatter.hpp"
+#include "launch.hpp"
+
+namespace simk {
+
+// ---------------------------------------------------------------------------
+// Column pass.  Block = CPB adjacent columns x TPS threads per column; each
+// thread holds E = 16 spectral samples of its column at rows s + m * TPS.
+//
+// With zeta(k, t) = 1/2 [c(k) e^{-i w t} + conj(c(-k)) e^{+i w t}] (Hermitian
+// in k) and its increment dzeta over dt, every real field F with multiplier
+// M_F has spectrum M_F zeta, and two real fields F1, F2 are carried by one
+// complex transform of M_F1 zeta + i M_F2 zeta.  Plane layout:
+//   0: h  + i Dx      1: Dy + i h_x     2: h_y + i Dx_x
+//   3: Dx_y + i Dy_y  4: dh + i dDx     5: dDy
+template <typename Real>
+__global__ void __launch_bounds__(512)
+colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
+               double t, double dt, int CPB, const cplx<Real>* __restrict__ tw) {
+  constexpr int E = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<Real>* lds = reinterpret_cast<cplx<Real>*>(smem_raw);
+  const int nx = gp.nx, ny = gp.ny;
+  const int TPS = ny / E;
+  const int c = threadIdx.x % CPB;
+  const int s = threadIdx.x / CPB;
+  const int ix = blockIdx.x * CPB + c;
+  const int mx = (nx - ix) & (nx - 1);
+  const double twopi = 6.283185307179586476925;
+  const double dkx = twopi / ((double)nx * gp.dx);
+  const double dky = twopi / ((double)ny * gp.dy);
+  const int nxs = ix < nx / 2 ? ix : ix - nx;
+  const double kx = dkx * (double)nxs;
+  const Real dcw = gp.cwm ? (Real)1 : (Real)0;
+
+  cplx<Real> zeta[E], dzeta[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int iy = s + m * TPS;
+    const int my = (ny - iy) & (ny - 1);
+    const int nys = iy < ny / 2 ? iy : iy - ny;
+    const bool skip = (ix == nx / 2) || (iy == ny / 2) || (ix == 0 && iy == 0);
+    cplx<Real> z = mk<Real>(0, 0), dz = mk<Real>(0, 0);
+    if (!skip) {
+      const cplx<Real> h0 = spec[(size_t)iy * nx + ix];
+      const cplx<Real> hm = spec[(size_t)my * nx + mx];
+      const double ky = dky * (double)nys;
+      const double kk = __builtin_sqrt(kx * kx + ky * ky);
+      const double w = __builtin_sqrt(gp.gravity * kk);
+      double rev = w * t * (1.0 / twopi);
+      rev -= __builtin_rint(rev);
+      Real sn, cs;
+      sincos_pi((Real)(2.0 * rev), &sn, &cs);
+      // p = 1/2 c(k) e^{-iwt}, q = 1/2 conj(c(-k)) e^{+iwt}
+      const cplx<Real> p = mk<Real>((Real)0.5 * (h0.x * cs + h0.y * sn),
+                                    (Real)0.5 * (h0.y * cs - h0.x * sn));
+      const cplx<Real> q = mk<Real>((Real)0.5 * (hm.x * cs + hm.y * sn),
+                                    (Real)0.5 * (hm.x * sn - hm.y * cs));
+      z = cadd(p, q);
+      // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt)
+      const double a = w * dt;
+      Real sh, sf;
+      if (a < 0.01) {
+        const double a2 = a * a;
+        const double s_half = 0.5 * a * (1.0 - a2 / 24.0 * (1.0 - a2 / 80.0 * (1.0 - a2 / 168.0)));
+        const double s_full = a * (1.0 - a2 / 6.0 * (1.0 - a2 / 20.0 * (1.0 - a2 / 42.0)));
+        sh = (Real)s_half;
+        sf = (Real)s_full;
+      } else {
+        sh = (Real)sin(0.5 * a);
+        sf = (Real)sin(a);
+      }
+      const cplx<Real> al = mk<Real>((Real)-2 * sh * sh, -sf);
+      dz = cadd(cmul(p, al), cmul(q, cconj(al)));
+    }
+    zeta[m] = z;
+    dzeta[m] = dz;
+  }
+
+  const Real kxr = (Real)kx;
+  cplx<Real>* lseq = lds + c;
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    cplx<Real> v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int iy = s + m * TPS;
+      const int nys = iy < ny / 2 ? iy : iy - ny;
+      const Real ky = (Real)dky * (Real)nys;
+      const Real k2 = kxr * kxr + ky * ky;
+      const Real ik = k2 > (Real)0 ? rsqrt(k2) : (Real)0;
+      const cplx<Real> z = (f < 4) ? zeta[m] : dzeta[m];
+      cplx<Real> mul;
+      switch (f) {
+        case 0:
+        case 4: mul = mk<Real>((Real)1 - dcw * kxr * ik, (Real)0); break;
+        case 1: mul = mk<Real>(-kxr, dcw * ky * ik); break;
+        case 2: mul = mk<Real>((Real)0, ky - dcw * kxr * kxr * ik); break;
+        case 3: mul = mk<Real>(-dcw * kxr * ky * ik, -dcw * ky * ky * ik); break;
+        default: mul = mk<Real>((Real)0, dcw * ky * ik); break;
+      }
+      v[m] = cmul(z, mul);
+    }
+    fft_seq<Real, E, +1>(v, lseq, CPB, ny, gp.log2ny, s, tw);
+    cplx<Real>* out = planes + (size_t)f * nx * ny;
+#pragma unroll
+    for (int m = 0; m < E; ++m) out[(size_t)(s + m * TPS) * nx + ix] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass helpers.  Block = RPB rows x TPR threads per row; each thread holds
+// ER = 8 samples of its row at columns tr + m * TPR.
+
+constexpr int ER = 8;
+
+template <typename Real>
+__device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, int nx, int iy,
+                                         bool valid, int tr, int TPR, cplx<Real>* v) {
+#pragma unroll
+  for (int m = 0; m < ER; ++m)
+    v[m] = valid ? plane[(size_t)iy * nx + tr + m * TPR] : mk<Real>(0, 0);
+}
+
+// Inverse transforms along x of the 6 planes for one row, reduced to the
+// nine facet quantities in the order they become available.
+template <typename Real>
+struct RowFacets {
+  Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
+};
+
+template <typename Real>
+__device__ __forceinline__ void row_facets(const cplx<Real>* __restrict__ planes, size_t plane_sz,
+                                           int nx, int log2nx, int iy, bool valid, int tr,
+                                           int TPR, cplx<Real>* lrow,
+                                           const cplx<Real>* __restrict__ tw, RowFacets<Real>& F) {
+  cplx<Real> v[ER];
+  Real hx[ER];
+  // plane 1: Dy + i h_x
+  load_row(planes + 1 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    F.Dy[m] = v[m].x;
+    hx[m] = v[m].y;
+  }
+  // plane 2: h_y + i Dx_x ; plane 3: Dx_y + i Dy_y
+  Real hy[ER], dxx[ER];
+  load_row(planes + 2 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    hy[m] = v[m].x;
+    dxx[m] = v[m].y;
+  }
+  load_row(planes + 3 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    const Real dxy = v[m].x, dyy = v[m].y;
+    // n = r_x x r_y with r_x = (1 + Dx_x, Dx_y, h_x), r_y = (Dx_y, 1 + Dy_y, h_y)
+    const Real nxn = dxy * hy[m] - hx[m] * ((Real)1 + dyy);
+    const Real nyn = hx[m] * dxy - ((Real)1 + dxx[m]) * hy[m];
+    const Real nzn = ((Real)1 + dxx[m]) * ((Real)1 + dyy) - dxy * dxy;
+    F.jac[m] = nzn;
+    F.sx[m] = -nxn / nzn;
+    F.sy[m] = -nyn / nzn;
+  }
+  // plane 0: h + i Dx
+  load_row(planes + 0 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    F.h[m] = v[m].x;
+    F.Dx[m] = v[m].y;
+  }
+  // plane 4: dh + i dDx ; plane 5: dDy
+  load_row(planes + 4 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    F.dh[m] = v[m].x;
+    F.dDx[m] = v[m].y;
+  }
+  load_row(planes + 5 * plane_sz, nx, iy, valid, tr, TPR, v);
+  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+#pragma unroll
+  for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(512)
+rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs<Real> out,
+                      const cplx<Real>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nx = gp.nx, ny = gp.ny;
+  const int TPR = nx / ER;
+  const int RPB = blockDim.x / TPR;
+  const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
+  cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
+  const size_t psz = (size_t)nx * ny;
+  for (int iy0 = blockIdx.x * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
+    const int iy = iy0 + rl;
+    const bool valid = iy < ny;
+    RowFacets<Real> F;
+    row_facets(planes, psz, nx, gp.log2nx, iy, valid, tr, TPR, lrow, tw, F);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < ER; ++m) {
+        const size_t o = (size_t)iy * nx + tr + m * TPR;
+        out.p[0][o] = F.Dx[m];
+        out.p[1][o] = F.Dy[m];
+        out.p[2][o] = F.h[m];
+        out.p[3][o] = F.sx[m];
+        out.p[4][o] = F.sy[m];
+        out.p[5][o] = F.jac[m];
+        out.p[6][o] = F.dDx[m];
+        out.p[7][o] = F.dDy[m];
+        out.p[8][o] = F.dh[m];
+      }
+    }
+  }
+}
+
+// Shared LDS carve-up for the accumulating kernels: [fft rows][window][state]
+template <typename Real>
+__device__ __forceinline__ WinCtx<Real> win_ctx(unsigned char* smem, size_t fft_bytes,
+                                                const RadarP& rp, const WinP& wp,
+                                                cplx<Real>* Tj, int band) {
+  WinCtx<Real> w;
+  w.win = reinterpret_cast<cplx<Real>*>(smem + fft_bytes);
+  int* ints = reinterpret_cast<int*>(smem + fft_bytes + (size_t)rp.G * wp.WK * sizeof(cplx<Real>));
+  w.st = ints;
+  w.red = ints + 8;
+  w.Tj = Tj;
+  w.band = band;
+  return w;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(512)
+rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, RadarP rp, WinP wp,
+                          cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out,
+                          const cplx<Real>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nx = gp.nx, ny = gp.ny;
+  const int TPR = nx / ER;
+  const int RPB = blockDim.x / TPR;
+  const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
+  const size_t fft_bytes = (size_t)RPB * lpad(nx) * sizeof(cplx<Real>);
+  cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
+  const int band = blockIdx.x;
+  WinCtx<Real> w = win_ctx<Real>(smem_raw, fft_bytes, rp, wp, Tj, band);
+  win_init(w, rp, wp);
+  uint32_t cnt[5] = {0, 0, 0, 0, 0};
+  uint32_t overflow = 0;
+  const size_t psz = (size_t)nx * ny;
+  const int row_begin = band * wp.band_rows;
+  const int row_end = min(ny, row_begin + wp.band_rows);
+  for (int iy0 = row_begin; iy0 < row_begin + wp.band_rows; iy0 += RPB) {
+    const int iy = iy0 + rl;
+    const bool valid = iy < row_end;
+    RowFacets<Real> F;
+    row_facets(planes, psz, nx, gp.log2nx, iy, valid, tr, TPR, lrow, tw, F);
+    int key[ER];
+    cplx<Real> cv[ER];
+#pragma unroll
+    for (int m = 0; m < ER; ++m) {
+      const int ix = tr + m * TPR;
+      key[m] = -100;
+      cv[m] = mk<Real>(0, 0);
+      if (valid) {
+        key[m] = scatterer<Real>(rp, gp, ix, iy, F.Dx[m], F.Dy[m], F.h[m], F.sx[m], F.sy[m],
+                                 F.jac[m], F.dDx[m], F.dDy[m], F.dh[m], cv[m]);
+        count_code(key[m], cnt);
+        if (code_out) code_out[(size_t)iy * nx + ix] = key[m];
+      }
+    }
+    win_add<Real, ER>(w, rp, wp, key, cv, overflow);
+  }
+  win_finish(w, rp, wp, overflow);
+  store_band_counts(wp, band, cnt, overflow, w.red);
+}
+
+// ---------------------------------------------------------------------------
+// Scatterers from a facet SoA: band = contiguous facet range, chunks of
+// EA * blockDim facets.
+constexpr int EA = 4;
+
+template <typename Real>
+__global__ void __launch_bounds__(256)
+accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
+                         cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int band = blockIdx.x;
+  WinCtx<Real> w = win_ctx<Real>(smem_raw, 0, rp, wp, Tj, band);
+  win_init(w, rp, wp);
+  uint32_t cnt[5] = {0, 0, 0, 0, 0};
+  uint32_t overflow = 0;
+  const size_t nfac = (size_t)gp.nx * gp.ny;
+  const size_t f_begin = (size_t)band * wp.band_rows;
+  const size_t f_end = min(nfac, f_begin + (size_t)wp.band_rows);
+  for (size_t c0 = f_begin; c0 < f_begin + (size_t)wp.band_rows; c0 += (size_t)EA * blockDim.x) {
+    int key[EA];
+    cplx<Real> cv[EA];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const size_t f = c0 + threadIdx.x + (size_t)e * blockDim.x;
+      key[e] = -100;
+      cv[e] = mk<Real>(0, 0);
+      if (f < f_end) {
+        const int iy = (int)(f >> gp.log2nx);
+        const int ix = (int)(f & (size_t)(gp.nx - 1));
+        key[e] = scatterer<Real>(rp, gp, ix, iy, fac.p[0][f], fac.p[1][f], fac.p[2][f],
+                                 fac.p[3][f], fac.p[4][f], fac.p[5][f], fac.p[6][f],
+                                 fac.p[7][f], fac.p[8][f], cv[e]);
+        count_code(key[e], cnt);
+        if (code_out) code_out[f] = key[e];
+      }
+    }
+    win_add<Real, EA>(w, rp, wp, key, cv, overflow);
+  }
+  win_finish(w, rp, wp, overflow);
+  store_band_counts(wp, band, cnt, overflow, w.red);
+}
+
+// ---------------------------------------------------------------------------
+// Ordered reduction of the band windows into T_fast[j]: one block per gate.
+// Slots covering the gate are compacted in slot order; every bin then sums
+// its contributions in that order (double accumulators), so the result is
+// independent of scheduling.  Block 0 also adds the band counters.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
+                       unsigned long long* __restrict__ counters) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int* list = reinterpret_cast<int*>(smem_raw);           // [n_slots]
+  int* lk0 = list + wp.n_bands * wp.S;                     // [n_slots]
+  __shared__ int wcount[16];
+  const int g = blockIdx.x;
+  const int nslots = wp.n_bands * wp.S;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  int base = 0;
+  for (int s0 = 0; s0 < nslots; s0 += blockDim.x) {
+    const int s = s0 + threadIdx.x;
+    bool take = false;
+    int k0 = 0;
+    if (s < nslots) {
+      const int4 h = wp.hdr[s];
+      take = h.x != 0 && g >= h.z && g <= h.w;
+      k0 = h.y;
+    }
+    const unsigned long long bal = __ballot(take);
+    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wv] = __popcll(bal);
+    __syncthreads();
+    int off = base, tot = 0;
+    for (int w2 = 0; w2 < nw; ++w2) {
+      if (w2 < wv) off += wcount[w2];
+      tot += wcount[w2];
+    }
+    if (take) {
+      list[off + rank] = s;
+      lk0[off + rank] = k0;
+    }
+    __syncthreads();
+    base += tot;
+  }
+  const int N = rp.N, WK = wp.WK;
+  const cplx<Real>* part = (const cplx<Real>*)wp.part;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    double ax = 0.0, ay = 0.0;
+    for (int i = 0; i < base; ++i) {
+      const int d = (k - lk0[i]) & (N - 1);
+      if (d < WK) {
+        const cplx<Real> v = part[((size_t)list[i] * rp.G + g) * WK + d];
+        ax += (double)v.x;
+        ay += (double)v.y;
+      }
+    }
+    cplx<Real> t = Tj[(size_t)g * N + k];
+    t.x = (Real)((double)t.x + ax);
+    t.y = (Real)((double)t.y + ay);
+    Tj[(size_t)g * N + k] = t;
+  }
+  if (blockIdx.x == 0 && counters != nullptr) {
+    unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < wp.n_bands; b += blockDim.x)
+      for (int i = 0; i < 6; ++i) v[i] += wp.bandcnt[(size_t)b * 8 + i];
+    __shared__ unsigned long long red[6][16];
+    for (int i = 0; i < 6; ++i) {
+      unsigned long long x = v[i];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) red[i][wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      unsigned long long s = 0;
+      for (int w2 = 0; w2 < nw; ++w2) s += red[threadIdx.x][w2];
+      counters[threadIdx.x] += s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Post-processing: block = (gate group, segment j).  The spectra j and j + 1
+// of GB gates are inverse transformed in LDS (radix-2 Stockham, ping-pong)
+// and the pulses [j n_fast, (j + 1) n_fast) of those gates are formed.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+segments_to_iq_kernel(const cplx<Real>* __restrict__ T, cplx<Real>* __restrict__ Y, int G, int N,
+                      int log2N, int n_fast, int window, int GB,
+                      const cplx<Real>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nseq = 2 * GB;
+  cplx<Real>* bufA = reinterpret_cast<cplx<Real>*>(smem_raw);
+  cplx<Real>* bufB = bufA + (size_t)nseq * N;
+  const int g0 = blockIdx.x * GB;
+  const int j = blockIdx.y;
+  for (int i = threadIdx.x; i < nseq * N; i += blockDim.x) {
+    const int sq = i / N, k = i - sq * N;
+    const int g = g0 + (sq % GB), jj = j + sq / GB;
+    bufA[i] = (g < G) ? T[((size_t)jj * G + g) * N + k] : mk<Real>(0, 0);
+  }
+  __syncthreads();
+  cplx<Real>* src = bufA;
+  cplx<Real>* dst = bufB;
+  const int half = N / 2;
+  for (int Ns = 1; Ns < N; Ns <<= 1) {
+    for (int i = threadIdx.x; i < nseq * half; i += blockDim.x) {
+      const int sq = i / half, b = i - sq * half;
+      const int jb = b & (Ns - 1);
+      const cplx<Real>* in = src + (size_t)sq * N;
+      cplx<Real>* out = dst + (size_t)sq * N;
+      const cplx<Real> a = in[b];
+      const cplx<Real> w = tw[jb * (kTwSize / (2 * Ns))];
+      const cplx<Real> c = cmul(in[b + half], w);
+      const int o = (b - jb) * 2 + jb;
+      out[o] = cadd(a, c);
+      out[o + Ns] = csub(a, c);
+    }
+    __syncthreads();
+    cplx<Real>* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  for (int i = threadIdx.x; i < n_fast * GB; i += blockDim.x) {
+    const int xl = i / GB, gl = i - xl * GB;
+    const int g = g0 + gl;
+    if (g >= G) continue;
+    const int d0 = xl, d1 = xl - n_fast;
+    // eq. (1) with |d| <= n_fast; the numerators are exact integers
+    double w0, w1;
+    if (window == 0) {
+      w0 = __builtin_sqrt((double)(n_fast - d0) / (double)n_fast);
+      w1 = __builtin_sqrt((double)(n_fast + d1) / (double)n_fast);
+    } else {
+      w0 = cos(1.5707963267948966192 * ((double)d0 / (double)n_fast));
+      w1 = cos(1.5707963267948966192 * ((double)d1 / (double)n_fast));
+    }
+    const cplx<Real> s0 = src[(size_t)gl * N + (d0 & (N - 1))];
+    const cplx<Real> s1 = src[(size_t)(GB + gl) * N + (d1 & (N - 1))];
+    cplx<Real> y = cadd(cscale(s0, (Real)w0), cscale(s1, (Real)w1));
+    Y[((size_t)j * n_fast + xl) * G + g] = y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launch wrappers.
+
+// Allow every kernel `lds` bytes of dynamic LDS (the device limit per block).
+hipError_t init_kernel_attributes(int lds) {
+  const void* fns[] = {
+      (const void*)colpass_kernel<float>,          (const void*)colpass_kernel<double>,
+      (const void*)rowpass_facets_kernel<float>,   (const void*)rowpass_facets_kernel<double>,
+      (const void*)rowpass_accumulate_kernel<float>, (const void*)rowpass_accumulate_kernel<double>,
+      (const void*)accumulate_facets_kernel<float>, (const void*)accumulate_facets_kernel<double>,
+      (const void*)reduce_partials_kernel<float>,  (const void*)reduce_partials_kernel<double>,
+      (const void*)segments_to_iq_kernel<float>,   (const void*)segments_to_iq_kernel<double>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename Real>
+hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
+                          const ColPlan& pl, const void* tw, hipStream_t st) {
+  hipLaunchKernelGGL(colpass_kernel<Real>, dim3(gp.nx / pl.cpb), dim3(pl.threads), pl.lds_bytes,
+                     st, (const cplx<Real>*)spec, (cplx<Real>*)planes, gp, t, dt, pl.cpb,
+                     (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_rowpass_facets(const void* planes, const GridP& gp, void* const* out,
+                                 const RowPlan& pl, const void* tw, hipStream_t st) {
+  FacetPtrs<Real> fp;
+  for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)out[i];
+  const int blocks = (gp.ny + pl.rpb - 1) / pl.rpb;
+  hipLaunchKernelGGL(rowpass_facets_kernel<Real>, dim3(blocks), dim3(pl.threads), pl.fft_bytes,
+                     st, (const cplx<Real>*)planes, gp, fp, (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_rowpass_accumulate(const void* planes, const GridP& gp, const RadarP& rp,
+                                     const WinP& wp, void* Tj, int32_t* code,
+                                     const RowPlan& pl, const void* tw, hipStream_t st) {
+  hipLaunchKernelGGL(rowpass_accumulate_kernel<Real>, dim3(wp.n_bands), dim3(pl.threads),
+                     pl.acc_bytes, st, (const cplx<Real>*)planes, gp, rp, wp, (cplx<Real>*)Tj,
+                     code, (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_accumulate_facets(void* const* fac, const GridP& gp, const RadarP& rp,
+                                    const WinP& wp, void* Tj, int32_t* code, size_t lds_bytes,
+                                    hipStream_t st) {
+  FacetPtrs<Real> fp;
+  for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)fac[i];
+  hipLaunchKernelGGL(accumulate_facets_kernel<Real>, dim3(wp.n_bands), dim3(256), lds_bytes, st,
+                     fp, gp, rp, wp, (cplx<Real>*)Tj, code);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_reduce(const RadarP& rp, const WinP& wp, void* Tj, unsigned long long* counters,
+                         hipStream_t st) {
+  const size_t lds = (size_t)2 * wp.n_bands * wp.S * sizeof(int);
+  hipLaunchKernelGGL(reduce_partials_kernel<Real>, dim3(rp.G), dim3(256), lds, st, rp, wp,
+                     (cplx<Real>*)Tj, counters);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_segments_to_iq(const void* T, void* Y, int G, int N, int log2N, int n_fast,
+                                 int window, int n_seg, int GB, const void* tw, hipStream_t st) {
+  const size_t lds = (size_t)2 * 2 * GB * N * sizeof(cplx<Real>);
+  hipLaunchKernelGGL(segments_to_iq_kernel<Real>, dim3((G + GB - 1) / GB, n_seg), dim3(256), lds,
+                     st, (const cplx<Real>*)T, (cplx<Real>*)Y, G, N, log2N, n_fast, window, GB,
+                     (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+#define SIMK_INSTANTIATE(R)                                                                      \
+  template hipError_t launch_colpass<R>(const void*, void*, const GridP&, double, double,       \
+                                        const ColPlan&, const void*, hipStream_t);              \
+  template hipError_t launch_rowpass_facets<R>(const void*, const GridP&, void* const*,         \
+                                               const RowPlan&, const void*, hipStream_t);       \
+  template hipError_t launch_rowpass_accumulate<R>(const void*, const GridP&, const RadarP&,     \
+                                                   const WinP&, void*, int32_t*,                \
+                                                   const RowPlan&, const void*, hipStream_t);   \
+  template hipError_t launch_accumulate_facets<R>(void* const*, const GridP&, const RadarP&,    \
+                                                  const WinP&, void*, int32_t*, size_t,         \
+                                                  hipStream_t);                                 \
+  template hipError_t launch_reduce<R>(const RadarP&, const WinP&, void*, unsigned long long*,  \
+                                       hipStream_t);                                            \
+  template hipError_t launch_segments_to_iq<R>(const void*, void*, int, int, int, int, int, int, \
+                                               int, const void*, hipStream_t);
+
+SIMK_INSTANTIATE(float)
+SIMK_INSTANTIATE(double)
+
+}  // namespace simk
