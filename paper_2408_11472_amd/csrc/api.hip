@@ -149,6 +149,7 @@ void fill_grid(const sim_grid* g, GridP& gp) {
   gp.x_origin = g->x_origin;
   gp.y_origin = g->y_origin;
   gp.gravity = g->gravity;
+  gp.sqrt_g = std::sqrt(g->gravity);
 }
 
 // Platform positions, Doppler constant and amplitude constants.  The double

@@ -37,6 +37,15 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk(a.x, -a.y); }
 __device__ __forceinline__ void sincos_pi(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sincos_pi(double x, double* s, double* c) { sincospi(x, s, c); }
 
+// 1/sqrt(x) in double from the float estimate and two Newton steps
+// (relative error ~1e-16 for x in the float range).
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = (double)__builtin_amdgcn_rsqf((float)x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
 // Size of the master twiddle table e^{+2 pi i m / kTwSize}.
 constexpr int kTwLog2 = 16;
 constexpr int kTwSize = 1 << kTwLog2;
@@ -274,7 +283,7 @@ __device__ __forceinline__ int block_max(int a, int* scratch) {
 struct GridP {
   int nx, ny, log2nx, log2ny;
   int cwm;
-  double dx, dy, x_origin, y_origin, gravity;
+  double dx, dy, x_origin, y_origin, gravity, sqrt_g;
 };
 
 struct RadarP {

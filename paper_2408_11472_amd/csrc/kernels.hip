@@ -37,7 +37,13 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
   const int TPS = ny / E;
   const int c = threadIdx.x % CPB;
   const int s = threadIdx.x / CPB;
-  const int ix = blockIdx.x * CPB + c;
+  // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
+  // contiguous run of strips so that strips sharing cache lines meet in the
+  // same L2.
+  const int nblk = gridDim.x;
+  const int strip = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                    : blockIdx.x;
+  const int ix = strip * CPB + c;
   const int mx = (nx - ix) & (nx - 1);
   const double twopi = 6.283185307179586476925;
   const double dkx = twopi / ((double)nx * gp.dx);
@@ -58,8 +64,11 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       const cplx<Real> h0 = spec[(size_t)iy * nx + ix];
       const cplx<Real> hm = spec[(size_t)my * nx + mx];
       const double ky = dky * (double)nys;
-      const double kk = __builtin_sqrt(kx * kx + ky * ky);
-      const double w = __builtin_sqrt(gp.gravity * kk);
+      // w = sqrt(g) (kx^2 + ky^2)^(1/4): two reciprocal square roots refined
+      // by Newton steps in double from the float estimate
+      const double q2 = kx * kx + ky * ky;
+      const double r1 = rsqrt_refined(q2);
+      const double w = gp.sqrt_g * rsqrt_refined(r1);
       double rev = w * t * (1.0 / twopi);
       rev -= __builtin_rint(rev);
       Real sn, cs;
@@ -71,17 +80,15 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
                                     (Real)0.5 * (hm.x * sn - hm.y * cs));
       z = cadd(p, q);
       // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt)
-      const double a = w * dt;
+      const Real a = (Real)(w * dt);
       Real sh, sf;
-      if (a < 0.01) {
-        const double a2 = a * a;
-        const double s_half = 0.5 * a * (1.0 - a2 / 24.0 * (1.0 - a2 / 80.0 * (1.0 - a2 / 168.0)));
-        const double s_full = a * (1.0 - a2 / 6.0 * (1.0 - a2 / 20.0 * (1.0 - a2 / 42.0)));
-        sh = (Real)s_half;
-        sf = (Real)s_full;
+      if (a < (Real)0.01) {
+        const Real a2 = a * a;
+        sh = (Real)0.5 * a * ((Real)1 - a2 / (Real)24 * ((Real)1 - a2 / (Real)80 * ((Real)1 - a2 / (Real)168)));
+        sf = a * ((Real)1 - a2 / (Real)6 * ((Real)1 - a2 / (Real)20 * ((Real)1 - a2 / (Real)42)));
       } else {
-        sh = (Real)sin(0.5 * a);
-        sf = (Real)sin(a);
+        sh = sin((Real)0.5 * a);
+        sf = sin(a);
       }
       const cplx<Real> al = mk<Real>((Real)-2 * sh * sh, -sf);
       dz = cadd(cmul(p, al), cmul(q, cconj(al)));
@@ -339,20 +346,29 @@ accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
 
 // ---------------------------------------------------------------------------
 // Ordered reduction of the band windows into T_fast[j]: one block per gate.
-// Slots covering the gate are compacted in slot order; every bin then sums
-// its contributions in that order (double accumulators), so the result is
-// independent of scheduling.  Block 0 also adds the band counters.
+// The slots covering the gate are compacted in slot order and cut into
+// contiguous chunks, one per wave.  Each wave adds its chunk, slot after
+// slot, into its own double accumulator in LDS (lanes = bins of the window,
+// a batch of loads in flight); the wave accumulators are then added in wave
+// order.  The association of the sum is fixed, so the result does not
+// depend on scheduling.  Block 0 also adds the band counters.
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceBatch = 8;
+
 template <typename Real>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kReduceThreads)
 reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
-                       unsigned long long* __restrict__ counters) {
+                       unsigned long long* __restrict__ counters, int n_acc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  int* list = reinterpret_cast<int*>(smem_raw);           // [n_slots]
-  int* lk0 = list + wp.n_bands * wp.S;                     // [n_slots]
+  const int nslots = wp.n_bands * wp.S;
+  const int N = rp.N, WK = wp.WK;
+  cplx<double>* acc = reinterpret_cast<cplx<double>*>(smem_raw);          // [n_acc][N]
+  int* list = reinterpret_cast<int*>(acc + (size_t)n_acc * N);             // [nslots]
+  int* lk0 = list + nslots;                                                // [nslots]
   __shared__ int wcount[16];
   const int g = blockIdx.x;
-  const int nslots = wp.n_bands * wp.S;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < n_acc * N; i += blockDim.x) acc[i] = mk<double>(0.0, 0.0);
   int base = 0;
   for (int s0 = 0; s0 < nslots; s0 += blockDim.x) {
     const int s = s0 + threadIdx.x;
@@ -379,17 +395,39 @@ reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
     __syncthreads();
     base += tot;
   }
-  const int N = rp.N, WK = wp.WK;
+  // wave wv < n_acc takes entries [lo, hi) in order
   const cplx<Real>* part = (const cplx<Real>*)wp.part;
+  if (wv < n_acc) {
+    const int per = (base + n_acc - 1) / n_acc;
+    const int lo = min(base, wv * per), hi = min(base, lo + per);
+    cplx<double>* a = acc + (size_t)wv * N;
+    for (int d0 = 0; d0 < WK; d0 += 64) {
+      const int d = d0 + lane;
+      for (int i0 = lo; i0 < hi; i0 += kReduceBatch) {
+        cplx<Real> v[kReduceBatch];
+#pragma unroll
+        for (int b = 0; b < kReduceBatch; ++b) {
+          v[b] = mk<Real>(0, 0);
+          if (i0 + b < hi && d < WK)
+            v[b] = part[((size_t)list[i0 + b] * rp.G + g) * WK + d];
+        }
+#pragma unroll
+        for (int b = 0; b < kReduceBatch; ++b) {
+          if (i0 + b < hi && d < WK) {
+            cplx<double>& c = a[(lk0[i0 + b] + d) & (N - 1)];
+            c.x += (double)v[b].x;
+            c.y += (double)v[b].y;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     double ax = 0.0, ay = 0.0;
-    for (int i = 0; i < base; ++i) {
-      const int d = (k - lk0[i]) & (N - 1);
-      if (d < WK) {
-        const cplx<Real> v = part[((size_t)list[i] * rp.G + g) * WK + d];
-        ax += (double)v.x;
-        ay += (double)v.y;
-      }
+    for (int w2 = 0; w2 < n_acc; ++w2) {
+      ax += acc[(size_t)w2 * N + k].x;
+      ay += acc[(size_t)w2 * N + k].y;
     }
     cplx<Real> t = Tj[(size_t)g * N + k];
     t.x = (Real)((double)t.x + ax);
@@ -408,9 +446,9 @@ reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-      unsigned long long s = 0;
-      for (int w2 = 0; w2 < nw; ++w2) s += red[threadIdx.x][w2];
-      counters[threadIdx.x] += s;
+      unsigned long long sum = 0;
+      for (int w2 = 0; w2 < nw; ++w2) sum += red[threadIdx.x][w2];
+      counters[threadIdx.x] += sum;
     }
   }
 }
@@ -541,9 +579,14 @@ hipError_t launch_accumulate_facets(void* const* fac, const GridP& gp, const Rad
 template <typename Real>
 hipError_t launch_reduce(const RadarP& rp, const WinP& wp, void* Tj, unsigned long long* counters,
                          hipStream_t st) {
-  const size_t lds = (size_t)2 * wp.n_bands * wp.S * sizeof(int);
-  hipLaunchKernelGGL(reduce_partials_kernel<Real>, dim3(rp.G), dim3(256), lds, st, rp, wp,
-                     (cplx<Real>*)Tj, counters);
+  // one double accumulator of N bins per wave, as many waves as 64 KiB allow
+  int n_acc = (int)(65536 / ((size_t)rp.N * sizeof(cplx<double>)));
+  if (n_acc > kReduceThreads / 64) n_acc = kReduceThreads / 64;
+  if (n_acc < 1) n_acc = 1;
+  const size_t lds = (size_t)n_acc * rp.N * sizeof(cplx<double>) +
+                     (size_t)2 * wp.n_bands * wp.S * sizeof(int);
+  hipLaunchKernelGGL(reduce_partials_kernel<Real>, dim3(rp.G), dim3(kReduceThreads), lds, st, rp,
+                     wp, (cplx<Real>*)Tj, counters, n_acc);
   return hipGetLastError();
 }
 

@@ -57,19 +57,25 @@ __device__ __forceinline__ int scatterer(const RadarP& rp, const GridP& gp, int 
     const double cyc = r * rp.k2;
     frac = cyc - __builtin_floor(cyc);
   }
-  // local incidence: tan^2 = |d x m|^2 / (d . m)^2 with m = (-sx, -sy, 1)
+  // local incidence: tan^2 = |d x m|^2 / (d . m)^2 with m = (-sx, -sy, 1);
+  // the cross product is formed in double (it differences ~1e5 m terms),
+  // the rest in Real
   const double msx = -(double)sx, msy = -(double)sy;
-  const double cx = ddy - ddz * msy;
-  const double cy = ddz * msx - ddx;
-  const double cz = ddx * msy - ddy * msx;
-  const Real tan2 = (Real)((cx * cx + cy * cy + cz * cz) / (q * q));
+  const Real cx = (Real)(ddy - ddz * msy);
+  const Real cy = (Real)(ddz * msx - ddx);
+  const Real cz = (Real)(ddx * msy - ddy * msx);
+  const Real qr = (Real)q;
+  const Real tan2 = (cx * cx + cy * cy + cz * cz) / (qr * qr);
   const Real sec2 = (Real)1 + tan2;
-  const Real sigma0 = (Real)rp.fresnel_over_mss * sec2 * sec2 * exp(-tan2 * (Real)rp.inv_mss);
+  const Real rr = (Real)r;
+  const Real fx = (Real)ddx, fy = (Real)ddy;
+  const Real sin2 = (fx * fx + fy * fy) / (rr * rr);
+  const Real hr = (Real)rp.altitude / rr;
+  // a = sqrt(sigma0 A) Ga (H/R)^2 with sigma0 = (|G0|^2/mss) sec^4 exp(-tan^2/mss)
+  // and Ga = exp(-(2/gamma) sin^2): one exponential for both
   const Real area = jac * sqrt((Real)1 + sx * sx + sy * sy) * (Real)rp.cell_area;
-  const Real sin2 = (Real)((ddx * ddx + ddy * ddy) / (r * r));
-  const Real ga = exp(-(Real)rp.two_over_gamma * sin2);
-  const Real hr = (Real)(rp.altitude / r);
-  const Real a = sqrt(sigma0 * area) * ga * hr * hr;
+  const Real ex = -(Real)0.5 * (Real)rp.inv_mss * tan2 - (Real)rp.two_over_gamma * sin2;
+  const Real a = sqrt((Real)rp.fresnel_over_mss * area) * sec2 * exp(ex) * hr * hr;
   Real sn, cs;
   sincos_pi((Real)2 * (Real)frac, &sn, &cs);
   C = mk<Real>(a * cs, -a * sn);
