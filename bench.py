@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--workload", default="track_4096")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 context")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="before timing, copy a buffer of this size once (a plain copy kernel "
+                        "of known traffic, to scale the HBM byte counters of a profiler run)")
     return p.parse_args()
 
 
@@ -100,6 +103,14 @@ def main():
 
     from paper_2408_11472_amd import inputs, workloads, simradar
 
+    if a.copy_calibration_mib > 0:
+        n = a.copy_calibration_mib * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = workloads.ALL[a.workload]()
     g = wl.grid
     spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh, wl.sea.peak_wavelength,

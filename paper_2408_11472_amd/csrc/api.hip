@@ -34,7 +34,7 @@ struct sim_ctx {
 
 namespace {
 
-constexpr size_t kLdsBudget = 159 * 1024;      // usable LDS per block
+using simk::kLdsBudget;
 constexpr size_t kWindowBudget = 32 * 1024;    // LDS of one window of partial spectra
 constexpr int kSlots = 4;                      // window slots per band
 constexpr int kMaxBands = 512;
@@ -85,13 +85,11 @@ sim_status check_radar(const sim_radar* r) {
 
 ColPlan col_plan(int nx, int ny, size_t cs) {
   ColPlan p;
-  const int tps = ny / 16;
-  int cpb = 16;
-  while (cpb > 1 && ((long)cpb * tps > 512 || (size_t)cpb * lpad(ny) * cs > kLdsBudget)) cpb >>= 1;
-  if (cpb > nx) cpb = nx;
-  p.cpb = cpb;
-  p.threads = cpb * tps;
-  p.lds_bytes = (size_t)cpb * lpad(ny) * cs;
+  const int l = ilog2(ny);
+  p.cpb = simk::col_cpb(l, (int)cs);
+  p.threads = simk::col_threads(l, (int)cs);
+  p.lds_bytes = simk::col_lds(l, (int)cs);
+  if (p.cpb > nx) p.lds_bytes = (size_t)-1;   // strips wider than the grid: unsupported
   return p;
 }
 
@@ -109,10 +107,10 @@ int window_bins(int G, int N, size_t cs, size_t fft_bytes) {
 
 RowPlan row_plan(int nx, size_t cs) {
   RowPlan p;
-  const int tpr = nx / 8;
-  p.rpb = tpr >= 256 ? 1 : 256 / tpr;
-  p.threads = p.rpb * tpr;
-  p.fft_bytes = (size_t)p.rpb * lpad(nx) * cs;
+  const int l = ilog2(nx);
+  p.rpb = simk::row_rpb(l);
+  p.threads = simk::row_threads(l);
+  p.fft_bytes = simk::row_fft_lds(l, (int)cs);
   p.acc_bytes = 0;
   return p;
 }
@@ -192,13 +190,18 @@ sim_status dev_err(hipError_t e, const char* what) {
 }
 #define dev(e) dev_err((e), #e)
 
+// Roots of unity per size (entries [M, 2M) hold e^{+2 pi i m / M}),
+// evaluated in long double and rounded once.
 template <typename Real>
 void make_twiddles(Real* host) {
   const long double two_pi = 6.283185307179586476925286766559L;
-  for (int m = 0; m < simk::kTwSize; ++m) {
-    const long double a = two_pi * (long double)m / (long double)simk::kTwSize;
-    host[2 * m] = (Real)cosl(a);
-    host[2 * m + 1] = (Real)sinl(a);
+  host[0] = host[1] = (Real)0;
+  for (int M = 1; M <= simk::kTwMax; M <<= 1) {
+    for (int m = 0; m < M; ++m) {
+      const long double a = two_pi * (long double)m / (long double)M;
+      host[2 * (M + m)] = (Real)cosl(a);
+      host[2 * (M + m) + 1] = (Real)sinl(a);
+    }
   }
 }
 
@@ -305,12 +308,13 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   sim_status s;
   {
     ProfScope p(c, SIM_KERNEL_SURFACE_COLPASS, st);
-    s = dev(simk::launch_colpass<Real>(spec0, planes, gp, t, 1.0 / r->prf_hz, cp, c->tw, st));
+    s = dev(simk::launch_colpass<Real>(spec0, planes, gp, t, 1.0 / r->prf_hz, c->tw, st));
   }
   if (s != SIM_OK) return s;
   {
     ProfScope p(c, SIM_KERNEL_FUSED_ROWPASS, st);
-    s = dev(simk::launch_rowpass_accumulate<Real>(planes, gp, rp, wp, Tj, code, rpl, c->tw, st));
+    s = dev(simk::launch_rowpass_accumulate<Real>(planes, gp, rp, wp, Tj, code, rpl.acc_bytes,
+                                                  c->tw, st));
   }
   if (s != SIM_OK) return s;
   ProfScope p(c, SIM_KERNEL_REDUCE_PARTIALS, st);
@@ -395,7 +399,7 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->profiling = false;
   c->used = 0;
   const size_t cs = csize(c);
-  const size_t bytes = (size_t)simk::kTwSize * cs;
+  const size_t bytes = (size_t)simk::kTwEntries * cs;
   if (dev(hipMalloc(&c->tw, bytes)) != SIM_OK) {
     delete c;
     return SIM_ERR_DEVICE;
@@ -476,7 +480,6 @@ sim_status sim_surface_update(sim_ctx* ctx, const sim_grid* grid, const void* sp
   const size_t cs = csize(ctx);
   const ColPlan cp = col_plan(grid->nx, grid->ny, cs);
   if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
-  const RowPlan rpl = row_plan(grid->nx, cs);
   void* const o[9] = {out->disp_x, out->disp_y, out->h, out->sx, out->sy, out->jac,
                       out->ddisp_x, out->ddisp_y, out->dh};
   hipStream_t st = (hipStream_t)stream;
@@ -484,13 +487,13 @@ sim_status sim_surface_update(sim_ctx* ctx, const sim_grid* grid, const void* sp
   const bool f64 = ctx->prec == SIM_PREC_FP64;
   {
     ProfScope p(ctx, SIM_KERNEL_SURFACE_COLPASS, st);
-    s = f64 ? dev(simk::launch_colpass<double>(spec0, planes, gp, t, dt_pair, cp, ctx->tw, st))
-            : dev(simk::launch_colpass<float>(spec0, planes, gp, t, dt_pair, cp, ctx->tw, st));
+    s = f64 ? dev(simk::launch_colpass<double>(spec0, planes, gp, t, dt_pair, ctx->tw, st))
+            : dev(simk::launch_colpass<float>(spec0, planes, gp, t, dt_pair, ctx->tw, st));
   }
   if (s != SIM_OK) return s;
   ProfScope p(ctx, SIM_KERNEL_SURFACE_ROWPASS, st);
-  return f64 ? dev(simk::launch_rowpass_facets<double>(planes, gp, o, rpl, ctx->tw, st))
-             : dev(simk::launch_rowpass_facets<float>(planes, gp, o, rpl, ctx->tw, st));
+  return f64 ? dev(simk::launch_rowpass_facets<double>(planes, gp, o, ctx->tw, st))
+             : dev(simk::launch_rowpass_facets<float>(planes, gp, o, ctx->tw, st));
 }
 
 sim_status sim_range_doppler_accumulate(sim_ctx* ctx, const sim_grid* grid,

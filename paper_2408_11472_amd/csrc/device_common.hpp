@@ -46,9 +46,12 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return y;
 }
 
-// Size of the master twiddle table e^{+2 pi i m / kTwSize}.
-constexpr int kTwLog2 = 16;
-constexpr int kTwSize = 1 << kTwLog2;
+// Twiddle table: for every power of two M <= kTwMax the M roots
+// e^{+2 pi i m / M}, m < M, stored contiguously at offset M (entries
+// [M, 2M)), so each transform size reads a compact slice.
+constexpr int kTwLog2 = 15;
+constexpr int kTwMax = 1 << kTwLog2;
+constexpr int kTwEntries = 2 * kTwMax;
 
 // v * e^{DIR 2 pi i k16 / 16} for a compile-time k16 (after unrolling).
 template <typename T, int DIR>
@@ -123,33 +126,33 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
 // bank pattern of the first Stockham stage).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
-// Twiddle w^r of a butterfly from the exact table powers w, w^2, w^4, w^8
-// (at most three products, compile-time r after unrolling).
-template <typename T>
-__device__ __forceinline__ cplx<T> twiddle_pow(const cplx<T>* base, int r) {
-  cplx<T> acc = mk<T>((T)1, (T)0);
-  bool first = true;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    if (r & (1 << b)) {
-      acc = first ? base[b] : cmul(acc, base[b]);
-      first = false;
-    }
+// Compile-time plan of an N = 2^LOG2N point transform held as E values per
+// thread (E in {8, 16}): an optional first stage of radix 2^(LOG2N mod log2 E),
+// then radix-E stages.
+template <int LOG2N, int E>
+struct FftPlan {
+  static constexpr int LE = (E == 16) ? 4 : 3;
+  static constexpr int REM = LOG2N % LE;
+  static constexpr int NSTAGES = LOG2N / LE + (REM ? 1 : 0);
+  static constexpr int radix(int s) { return (s == 0 && REM) ? (1 << REM) : E; }
+  static constexpr int ns(int s) {
+    int n = 1;
+    for (int i = 0; i < s; ++i) n *= radix(i);
+    return n;
   }
-  return acc;
-}
+};
 
-// One Stockham radix-R stage on a sequence of length N held as E values per
+// One Stockham radix-R stage on a sequence of N points held as E values per
 // thread by T = N/E threads: register slot m holds position tid + m*T.
 // Butterfly q (q < E/R) of this thread is b = tid + q*T with inputs at
-// slots q + r*(E/R).  The outputs go to LDS at the self-sorting positions
-// ((b - j) * R + j + r * Ns, j = b mod Ns), except on the last stage, whose
-// output positions coincide with the register slots.
-template <typename T, int E, int R, int DIR>
-__device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int ls, int N,
-                                               int tid, int Ns, bool last,
+// slots q + r*(E/R); its outputs go to the self-sorting positions
+// (b - j) * R + j + r * Ns, j = b mod Ns.  On the last stage those positions
+// coincide with the register slots, so the data stays in registers.  LDS
+// element i of the sequence lives at lds[lpad(i) * LS].
+template <typename T, int N, int E, int R, int Ns, bool LAST, int LS, int DIR>
+__device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid,
                                                const cplx<T>* __restrict__ tw) {
-  const int Tn = N / E;
+  constexpr int Tn = N / E;
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
     cplx<T> u[R];
@@ -158,65 +161,78 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int ls,
     const int b = tid + q * Tn;
     const int j = b & (Ns - 1);
     if (Ns > 1) {
-      // w = e^{DIR 2 pi i j / (Ns R)}: table entries j s, 2 j s, 4 j s, 8 j s
-      const int step = j * (kTwSize / (Ns * R));
-      cplx<T> base[4];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        if ((1 << bb) < R) {
-          base[bb] = tw[(step << bb) & (kTwSize - 1)];
-          if (DIR < 0) base[bb].y = -base[bb].y;
-        } else {
-          base[bb] = mk<T>((T)1, (T)0);
+      // u[r] *= w^r with w = e^{DIR 2 pi i j / (Ns R)}: w and w^4 are read
+      // from the size-(Ns R) slice of the table, the other powers are formed
+      // with at most three products and applied at once, so no power is
+      // kept live beyond its use.
+      const cplx<T>* twm = tw + Ns * R;
+      cplx<T> w1 = twm[(unsigned)j];
+      if (DIR < 0) w1.y = -w1.y;
+      const cplx<T> w2 = cmul(w1, w1);
+      const cplx<T> w3 = cmul(w2, w1);
+      u[1] = cmul(u[1], w1);
+      if (R > 2) u[2] = cmul(u[2], w2);
+      if (R > 3) u[3] = cmul(u[3], w3);
+      if (R > 4) {
+        cplx<T> w4 = twm[(unsigned)(4 * j)];
+        if (DIR < 0) w4.y = -w4.y;
+        u[4] = cmul(u[4], w4);
+        u[5] = cmul(u[5], cmul(w4, w1));
+        u[6] = cmul(u[6], cmul(w4, w2));
+        u[7] = cmul(u[7], cmul(w4, w3));
+        if (R > 8) {
+          const cplx<T> w8 = cmul(w4, w4);
+          u[8] = cmul(u[8], w8);
+          u[9] = cmul(u[9], cmul(w8, w1));
+          u[10] = cmul(u[10], cmul(w8, w2));
+          u[11] = cmul(u[11], cmul(w8, w3));
+          const cplx<T> w12 = cmul(w8, w4);
+          u[12] = cmul(u[12], w12);
+          u[13] = cmul(u[13], cmul(w12, w1));
+          u[14] = cmul(u[14], cmul(w12, w2));
+          u[15] = cmul(u[15], cmul(w12, w3));
         }
       }
-#pragma unroll
-      for (int r = 1; r < R; ++r) u[r] = cmul(u[r], twiddle_pow(base, r));
     }
     dft<T, R, DIR>(u);
-    if (last) {
+    if (LAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * (E / R)] = u[r];
     } else {
       const int base = (b - j) * R + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lpad(base + r * Ns) * ls] = u[r];
+      for (int r = 0; r < R; ++r) lds[lpad(base + r * Ns) * LS] = u[r];
     }
   }
-  if (!last) {
+  if (!LAST) {
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = lds[lpad(tid + m * Tn) * ls];
+    for (int m = 0; m < E; ++m) v[m] = lds[lpad(tid + m * Tn) * LS];
     __syncthreads();
   }
 }
 
-// Unnormalised DFT of one sequence of length N (power of two, N >= E),
+template <typename T, int LOG2N, int E, int LS, int DIR, int S>
+__device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, int tid,
+                                           const cplx<T>* __restrict__ tw) {
+  using P = FftPlan<LOG2N, E>;
+  if constexpr (S < P::NSTAGES) {
+    stockham_stage<T, (1 << LOG2N), E, P::radix(S), P::ns(S), S == P::NSTAGES - 1, LS, DIR>(
+        v, lds, tid, tw);
+    fft_stages<T, LOG2N, E, LS, DIR, S + 1>(v, lds, tid, tw);
+  }
+}
+
+// Unnormalised DFT of one sequence of N = 2^LOG2N points (N >= E),
 // X[k] = sum_n x[n] e^{DIR 2 pi i n k / N}, held in registers as E values
 // per thread in slot order (slot m = position tid + m*N/E) on entry and on
-// exit.  lds points at this sequence's LDS region (lpad(N) elements with
-// element stride ls).  Every thread of the block must call it (barriers).
-template <typename T, int E, int DIR>
-__device__ __forceinline__ void fft_seq(cplx<T>* v, cplx<T>* lds, int ls, int N, int log2N,
-                                        int tid, const cplx<T>* __restrict__ tw) {
-  constexpr int LE = (E == 16) ? 4 : (E == 8) ? 3 : (E == 4) ? 2 : 1;
-  const int full = log2N / LE;
-  const int rem = log2N - full * LE;
-  int Ns = 1;
-  if (rem == 1) {
-    stockham_stage<T, E, 2, DIR>(v, lds, ls, N, tid, Ns, false, tw);
-    Ns *= 2;
-  } else if (rem == 2) {
-    stockham_stage<T, E, (E >= 4 ? 4 : 2), DIR>(v, lds, ls, N, tid, Ns, false, tw);
-    Ns *= 4;
-  } else if (rem == 3) {
-    stockham_stage<T, E, (E >= 8 ? 8 : 2), DIR>(v, lds, ls, N, tid, Ns, false, tw);
-    Ns *= 8;
-  }
-  for (int s = 0; s < full; ++s) {
-    stockham_stage<T, E, E, DIR>(v, lds, ls, N, tid, Ns, s == full - 1, tw);
-    Ns *= E;
-  }
+// exit.  lds points at this sequence's LDS region (lpad(N) elements, element
+// stride LS).  Every thread of the block must call it (barriers).
+template <typename T, int LOG2N, int E, int LS, int DIR>
+__device__ __forceinline__ void fft_seq(cplx<T>* v, cplx<T>* lds, int tid,
+                                        const cplx<T>* __restrict__ tw) {
+  static_assert((1 << LOG2N) >= E, "transform shorter than the values per thread");
+  fft_stages<T, LOG2N, E, LS, DIR, 0>(v, lds, tid, tw);
 }
 
 // ---------------------------------------------------------------------------

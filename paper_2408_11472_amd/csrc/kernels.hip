@@ -26,23 +26,28 @@ namespace simk {
 // complex transform of M_F1 zeta + i M_F2 zeta.  Plane layout:
 //   0: h  + i Dx      1: Dy + i h_x     2: h_y + i Dx_x
 //   3: Dx_y + i Dy_y  4: dh + i dDx     5: dDy
-template <typename Real>
-__global__ void __launch_bounds__(512)
+// Each column strip is handled by two blocks: group 0 makes planes 0-3 from
+// zeta, group 1 planes 4-5 from dzeta, so a thread keeps one spectral state.
+template <typename Real, int LOG2NY>
+__global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
 colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
-               double t, double dt, int CPB, const cplx<Real>* __restrict__ tw) {
+               double t, double dt, const cplx<Real>* __restrict__ tw) {
   constexpr int E = 16;
+  constexpr int ny = 1 << LOG2NY;
+  constexpr int TPS = ny / E;
+  constexpr int CPB = col_cpb(LOG2NY, sizeof(cplx<Real>));
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<Real>* lds = reinterpret_cast<cplx<Real>*>(smem_raw);
-  const int nx = gp.nx, ny = gp.ny;
-  const int TPS = ny / E;
+  const int nx = gp.nx;
   const int c = threadIdx.x % CPB;
   const int s = threadIdx.x / CPB;
   // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
-  // contiguous run of strips so that strips sharing cache lines meet in the
-  // same L2.
+  // contiguous run of (strip, group) items so that the two groups of a strip
+  // and neighbouring strips, which share cache lines, meet in the same L2.
   const int nblk = gridDim.x;
-  const int strip = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
-                                    : blockIdx.x;
+  const int item = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                   : blockIdx.x;
+  const int strip = item >> 1, group = item & 1;
   const int ix = strip * CPB + c;
   const int mx = (nx - ix) & (nx - 1);
   const double twopi = 6.283185307179586476925;
@@ -52,14 +57,14 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
   const double kx = dkx * (double)nxs;
   const Real dcw = gp.cwm ? (Real)1 : (Real)0;
 
-  cplx<Real> zeta[E], dzeta[E];
+  cplx<Real> st[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int iy = s + m * TPS;
     const int my = (ny - iy) & (ny - 1);
     const int nys = iy < ny / 2 ? iy : iy - ny;
     const bool skip = (ix == nx / 2) || (iy == ny / 2) || (ix == 0 && iy == 0);
-    cplx<Real> z = mk<Real>(0, 0), dz = mk<Real>(0, 0);
+    cplx<Real> z = mk<Real>(0, 0);
     if (!skip) {
       const cplx<Real> h0 = spec[(size_t)iy * nx + ix];
       const cplx<Real> hm = spec[(size_t)my * nx + mx];
@@ -78,53 +83,62 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
                                     (Real)0.5 * (h0.y * cs - h0.x * sn));
       const cplx<Real> q = mk<Real>((Real)0.5 * (hm.x * cs + hm.y * sn),
                                     (Real)0.5 * (hm.x * sn - hm.y * cs));
-      z = cadd(p, q);
-      // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt)
-      const Real a = (Real)(w * dt);
-      Real sh, sf;
-      if (a < (Real)0.01) {
-        const Real a2 = a * a;
-        sh = (Real)0.5 * a * ((Real)1 - a2 / (Real)24 * ((Real)1 - a2 / (Real)80 * ((Real)1 - a2 / (Real)168)));
-        sf = a * ((Real)1 - a2 / (Real)6 * ((Real)1 - a2 / (Real)20 * ((Real)1 - a2 / (Real)42)));
+      if (group == 0) {
+        z = cadd(p, q);
       } else {
-        sh = sin((Real)0.5 * a);
-        sf = sin(a);
+        // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt)
+        const Real a = (Real)(w * dt);
+        Real sh, sf;
+        if (a < (Real)0.01) {
+          const Real a2 = a * a;
+          sh = (Real)0.5 * a *
+               ((Real)1 - a2 / (Real)24 * ((Real)1 - a2 / (Real)80 * ((Real)1 - a2 / (Real)168)));
+          sf = a * ((Real)1 - a2 / (Real)6 * ((Real)1 - a2 / (Real)20 * ((Real)1 - a2 / (Real)42)));
+        } else {
+          sh = sin((Real)0.5 * a);
+          sf = sin(a);
+        }
+        const cplx<Real> al = mk<Real>((Real)-2 * sh * sh, -sf);
+        z = cadd(cmul(p, al), cmul(q, cconj(al)));
       }
-      const cplx<Real> al = mk<Real>((Real)-2 * sh * sh, -sf);
-      dz = cadd(cmul(p, al), cmul(q, cconj(al)));
     }
-    zeta[m] = z;
-    dzeta[m] = dz;
+    st[m] = z;
+    __builtin_amdgcn_sched_barrier(0);
   }
 
-  const Real kxr = (Real)kx;
-  cplx<Real>* lseq = lds + c;
+  const int f0 = group == 0 ? 0 : 4;
+  const int f1 = group == 0 ? 4 : 6;
 #pragma unroll 1
-  for (int f = 0; f < 6; ++f) {
+  for (int f = f0; f < f1; ++f) {
+    // Opaque copies of the thread coordinates: everything derived from them
+    // (store addresses, wavenumbers, LDS offsets) is recomputed per field
+    // instead of being hoisted out of the loop and kept in registers.
+    int sv = s, ixv = ix;
+    asm volatile("" : "+v"(sv), "+v"(ixv));
+    const Real kxv = (Real)dkx * (Real)(ixv < nx / 2 ? ixv : ixv - nx);
     cplx<Real> v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int iy = s + m * TPS;
+      const int iy = sv + m * TPS;
       const int nys = iy < ny / 2 ? iy : iy - ny;
       const Real ky = (Real)dky * (Real)nys;
-      const Real k2 = kxr * kxr + ky * ky;
+      const Real k2 = kxv * kxv + ky * ky;
       const Real ik = k2 > (Real)0 ? rsqrt(k2) : (Real)0;
-      const cplx<Real> z = (f < 4) ? zeta[m] : dzeta[m];
       cplx<Real> mul;
       switch (f) {
         case 0:
-        case 4: mul = mk<Real>((Real)1 - dcw * kxr * ik, (Real)0); break;
-        case 1: mul = mk<Real>(-kxr, dcw * ky * ik); break;
-        case 2: mul = mk<Real>((Real)0, ky - dcw * kxr * kxr * ik); break;
-        case 3: mul = mk<Real>(-dcw * kxr * ky * ik, -dcw * ky * ky * ik); break;
+        case 4: mul = mk<Real>((Real)1 - dcw * kxv * ik, (Real)0); break;
+        case 1: mul = mk<Real>(-kxv, dcw * ky * ik); break;
+        case 2: mul = mk<Real>((Real)0, ky - dcw * kxv * kxv * ik); break;
+        case 3: mul = mk<Real>(-dcw * kxv * ky * ik, -dcw * ky * ky * ik); break;
         default: mul = mk<Real>((Real)0, dcw * ky * ik); break;
       }
-      v[m] = cmul(z, mul);
+      v[m] = cmul(st[m], mul);
     }
-    fft_seq<Real, E, +1>(v, lseq, CPB, ny, gp.log2ny, s, tw);
-    cplx<Real>* out = planes + (size_t)f * nx * ny;
+    fft_seq<Real, LOG2NY, E, CPB, +1>(v, lds + (ixv - strip * CPB), sv, tw);
+    cplx<Real>* out = planes + (size_t)f * nx * ny + ixv;
 #pragma unroll
-    for (int m = 0; m < E; ++m) out[(size_t)(s + m * TPS) * nx + ix] = v[m];
+    for (int m = 0; m < E; ++m) out[(size_t)(sv + m * TPS) * nx] = v[m];
   }
 }
 
@@ -132,49 +146,58 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
 // Row pass helpers.  Block = RPB rows x TPR threads per row; each thread holds
 // ER = 8 samples of its row at columns tr + m * TPR.
 
-constexpr int ER = 8;
+constexpr int ER = kRowE;
 
-template <typename Real>
-__device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, int nx, int iy,
-                                         bool valid, int tr, int TPR, cplx<Real>* v) {
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, int iy, bool valid,
+                                         int tr, cplx<Real>* v) {
+  constexpr int nx = 1 << LOG2NX, TPR = nx / ER;
+  const cplx<Real>* row = plane + (size_t)iy * nx + tr;
 #pragma unroll
-  for (int m = 0; m < ER; ++m)
-    v[m] = valid ? plane[(size_t)iy * nx + tr + m * TPR] : mk<Real>(0, 0);
+  for (int m = 0; m < ER; ++m) v[m] = valid ? row[m * TPR] : mk<Real>(0, 0);
 }
 
-// Inverse transforms along x of the 6 planes for one row, reduced to the
-// nine facet quantities in the order they become available.
+// Inverse transform along x of one plane for one row.  The thread
+// coordinate is made opaque per call, so that addresses and LDS offsets are
+// recomputed per transform instead of being kept live across all six.
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ plane, int iy,
+                                              bool valid, int tr, cplx<Real>* lrow,
+                                              const cplx<Real>* __restrict__ tw, cplx<Real>* v) {
+  int trv = tr;
+  asm volatile("" : "+v"(trv));
+  load_row<Real, LOG2NX>(plane, iy, valid, trv, v);
+  fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
+}
+
+// The nine facet quantities of one row, in the order they become available:
+// planes 1-3 give the normal (slopes, Jacobian), plane 0 the position,
+// planes 4-5 the displacement over the pulse pair.
 template <typename Real>
 struct RowFacets {
   Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
 };
 
-template <typename Real>
-__device__ __forceinline__ void row_facets(const cplx<Real>* __restrict__ planes, size_t plane_sz,
-                                           int nx, int log2nx, int iy, bool valid, int tr,
-                                           int TPR, cplx<Real>* lrow,
-                                           const cplx<Real>* __restrict__ tw, RowFacets<Real>& F) {
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes, size_t psz,
+                                           int iy, bool valid, int tr, cplx<Real>* lrow,
+                                           const cplx<Real>* __restrict__ tw,
+                                           RowFacets<Real>& F) {
   cplx<Real> v[ER];
-  Real hx[ER];
-  // plane 1: Dy + i h_x
-  load_row(planes + 1 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+  Real hx[ER], hy[ER], dxx[ER];
+  row_transform<Real, LOG2NX>(planes + 1 * psz, iy, valid, tr, lrow, tw, v);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
-  // plane 2: h_y + i Dx_x ; plane 3: Dx_y + i Dy_y
-  Real hy[ER], dxx[ER];
-  load_row(planes + 2 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+  row_transform<Real, LOG2NX>(planes + 2 * psz, iy, valid, tr, lrow, tw, v);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     hy[m] = v[m].x;
     dxx[m] = v[m].y;
   }
-  load_row(planes + 3 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+  row_transform<Real, LOG2NX>(planes + 3 * psz, iy, valid, tr, lrow, tw, v);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     const Real dxy = v[m].x, dyy = v[m].y;
@@ -186,36 +209,40 @@ __device__ __forceinline__ void row_facets(const cplx<Real>* __restrict__ planes
     F.sx[m] = -nxn / nzn;
     F.sy[m] = -nyn / nzn;
   }
-  // plane 0: h + i Dx
-  load_row(planes + 0 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+}
+
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
+                                           int iy, bool valid, int tr, cplx<Real>* lrow,
+                                           const cplx<Real>* __restrict__ tw,
+                                           RowFacets<Real>& F) {
+  cplx<Real> v[ER];
+  row_transform<Real, LOG2NX>(planes + 0 * psz, iy, valid, tr, lrow, tw, v);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
-  // plane 4: dh + i dDx ; plane 5: dDy
-  load_row(planes + 4 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+  row_transform<Real, LOG2NX>(planes + 4 * psz, iy, valid, tr, lrow, tw, v);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.dh[m] = v[m].x;
     F.dDx[m] = v[m].y;
   }
-  load_row(planes + 5 * plane_sz, nx, iy, valid, tr, TPR, v);
-  fft_seq<Real, ER, +1>(v, lrow, 1, nx, log2nx, tr, tw);
+  row_transform<Real, LOG2NX>(planes + 5 * psz, iy, valid, tr, lrow, tw, v);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
 }
 
-template <typename Real>
-__global__ void __launch_bounds__(512)
+template <typename Real, int LOG2NX>
+__global__ void __launch_bounds__(row_threads(LOG2NX))
 rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs<Real> out,
                       const cplx<Real>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nx = gp.nx, ny = gp.ny;
-  const int TPR = nx / ER;
-  const int RPB = blockDim.x / TPR;
+  constexpr int nx = 1 << LOG2NX;
+  constexpr int TPR = row_tpr(LOG2NX);
+  constexpr int RPB = row_rpb(LOG2NX);
+  const int ny = gp.ny;
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
   const size_t psz = (size_t)nx * ny;
@@ -223,17 +250,24 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
     RowFacets<Real> F;
-    row_facets(planes, psz, nx, gp.log2nx, iy, valid, tr, TPR, lrow, tw, F);
+    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < ER; ++m) {
+        const size_t o = (size_t)iy * nx + tr + m * TPR;
+        out.p[1][o] = F.Dy[m];
+        out.p[3][o] = F.sx[m];
+        out.p[4][o] = F.sy[m];
+        out.p[5][o] = F.jac[m];
+      }
+    }
+    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
         const size_t o = (size_t)iy * nx + tr + m * TPR;
         out.p[0][o] = F.Dx[m];
-        out.p[1][o] = F.Dy[m];
         out.p[2][o] = F.h[m];
-        out.p[3][o] = F.sx[m];
-        out.p[4][o] = F.sy[m];
-        out.p[5][o] = F.jac[m];
         out.p[6][o] = F.dDx[m];
         out.p[7][o] = F.dDy[m];
         out.p[8][o] = F.dh[m];
@@ -257,15 +291,16 @@ __device__ __forceinline__ WinCtx<Real> win_ctx(unsigned char* smem, size_t fft_
   return w;
 }
 
-template <typename Real>
-__global__ void __launch_bounds__(512)
+template <typename Real, int LOG2NX>
+__global__ void __launch_bounds__(row_threads(LOG2NX))
 rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, RadarP rp, WinP wp,
                           cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out,
                           const cplx<Real>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nx = gp.nx, ny = gp.ny;
-  const int TPR = nx / ER;
-  const int RPB = blockDim.x / TPR;
+  constexpr int nx = 1 << LOG2NX;
+  constexpr int TPR = row_tpr(LOG2NX);
+  constexpr int RPB = row_rpb(LOG2NX);
+  const int ny = gp.ny;
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   const size_t fft_bytes = (size_t)RPB * lpad(nx) * sizeof(cplx<Real>);
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
@@ -281,20 +316,28 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
     const int iy = iy0 + rl;
     const bool valid = iy < row_end;
     RowFacets<Real> F;
-    row_facets(planes, psz, nx, gp.log2nx, iy, valid, tr, TPR, lrow, tw, F);
+    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
+    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
     int key[ER];
     cplx<Real> cv[ER];
+    // opaque row coordinates: the grid positions of the facets are
+    // recomputed per row rather than kept live across the row loop
+    int trv = tr, iyv = iy;
+    asm volatile("" : "+v"(trv), "+v"(iyv));
 #pragma unroll
     for (int m = 0; m < ER; ++m) {
-      const int ix = tr + m * TPR;
+      const int ix = trv + m * TPR;
       key[m] = -100;
       cv[m] = mk<Real>(0, 0);
       if (valid) {
-        key[m] = scatterer<Real>(rp, gp, ix, iy, F.Dx[m], F.Dy[m], F.h[m], F.sx[m], F.sy[m],
+        key[m] = scatterer<Real>(rp, gp, ix, iyv, F.Dx[m], F.Dy[m], F.h[m], F.sx[m], F.sy[m],
                                  F.jac[m], F.dDx[m], F.dDy[m], F.dh[m], cv[m]);
         count_code(key[m], cnt);
-        if (code_out) code_out[(size_t)iy * nx + ix] = key[m];
+        if (code_out) code_out[(size_t)iyv * nx + ix] = key[m];
       }
+      // one facet at a time: keeps the double temporaries of a single
+      // scatterer live instead of eight
+      __builtin_amdgcn_sched_barrier(0);
     }
     win_add<Real, ER>(w, rp, wp, key, cv, overflow);
   }
@@ -484,7 +527,7 @@ segments_to_iq_kernel(const cplx<Real>* __restrict__ T, cplx<Real>* __restrict__
       const cplx<Real>* in = src + (size_t)sq * N;
       cplx<Real>* out = dst + (size_t)sq * N;
       const cplx<Real> a = in[b];
-      const cplx<Real> w = tw[jb * (kTwSize / (2 * Ns))];
+      const cplx<Real> w = tw[2 * Ns + jb];
       const cplx<Real> c = cmul(in[b + half], w);
       const int o = (b - jb) * 2 + jb;
       out[o] = cadd(a, c);
@@ -517,52 +560,84 @@ segments_to_iq_kernel(const cplx<Real>* __restrict__ T, cplx<Real>* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Host launch wrappers.
+// Host launch wrappers.  The FFT kernels are instantiated for every
+// supported power-of-two side and selected here by log2 of the side.
 
-// Allow every kernel `lds` bytes of dynamic LDS (the device limit per block).
-hipError_t init_kernel_attributes(int lds) {
-  const void* fns[] = {
-      (const void*)colpass_kernel<float>,          (const void*)colpass_kernel<double>,
-      (const void*)rowpass_facets_kernel<float>,   (const void*)rowpass_facets_kernel<double>,
-      (const void*)rowpass_accumulate_kernel<float>, (const void*)rowpass_accumulate_kernel<double>,
-      (const void*)accumulate_facets_kernel<float>, (const void*)accumulate_facets_kernel<double>,
-      (const void*)reduce_partials_kernel<float>,  (const void*)reduce_partials_kernel<double>,
-      (const void*)segments_to_iq_kernel<float>,   (const void*)segments_to_iq_kernel<double>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
+#define SIMK_COL_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
+#define SIMK_ROW_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+
+template <typename Real, int L>
+static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, double t, double dt,
+                            const void* tw, hipStream_t st) {
+  constexpr int cs = sizeof(cplx<Real>);
+  if constexpr (col_lds(L, cs) > kLdsBudget) {
+    return hipErrorInvalidValue;
+  } else {
+    const int strips = gp.nx / col_cpb(L, cs);
+    hipLaunchKernelGGL((colpass_kernel<Real, L>), dim3(2 * strips), dim3(col_threads(L, cs)),
+                       col_lds(L, cs), st, (const cplx<Real>*)spec, (cplx<Real>*)planes, gp, t, dt,
+                       (const cplx<Real>*)tw);
+    return hipGetLastError();
   }
-  return hipSuccess;
 }
 
 template <typename Real>
 hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
-                          const ColPlan& pl, const void* tw, hipStream_t st) {
-  hipLaunchKernelGGL(colpass_kernel<Real>, dim3(gp.nx / pl.cpb), dim3(pl.threads), pl.lds_bytes,
-                     st, (const cplx<Real>*)spec, (cplx<Real>*)planes, gp, t, dt, pl.cpb,
+                          const void* tw, hipStream_t st) {
+  switch (gp.log2ny) {
+#define SIMK_CASE(L) \
+  case L: return colpass_t<Real, L>(spec, planes, gp, t, dt, tw, st);
+    SIMK_COL_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real, int L>
+static hipError_t rowpass_facets_t(const void* planes, const GridP& gp, const FacetPtrs<Real>& fp,
+                                   const void* tw, hipStream_t st) {
+  const int blocks = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
+  hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks), dim3(row_threads(L)),
+                     row_fft_lds(L, sizeof(cplx<Real>)), st, (const cplx<Real>*)planes, gp, fp,
                      (const cplx<Real>*)tw);
   return hipGetLastError();
 }
 
 template <typename Real>
 hipError_t launch_rowpass_facets(const void* planes, const GridP& gp, void* const* out,
-                                 const RowPlan& pl, const void* tw, hipStream_t st) {
+                                 const void* tw, hipStream_t st) {
   FacetPtrs<Real> fp;
   for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)out[i];
-  const int blocks = (gp.ny + pl.rpb - 1) / pl.rpb;
-  hipLaunchKernelGGL(rowpass_facets_kernel<Real>, dim3(blocks), dim3(pl.threads), pl.fft_bytes,
-                     st, (const cplx<Real>*)planes, gp, fp, (const cplx<Real>*)tw);
+  switch (gp.log2nx) {
+#define SIMK_CASE(L) \
+  case L: return rowpass_facets_t<Real, L>(planes, gp, fp, tw, st);
+    SIMK_ROW_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real, int L>
+static hipError_t rowpass_accumulate_t(const void* planes, const GridP& gp, const RadarP& rp,
+                                       const WinP& wp, void* Tj, int32_t* code, size_t lds,
+                                       const void* tw, hipStream_t st) {
+  hipLaunchKernelGGL((rowpass_accumulate_kernel<Real, L>), dim3(wp.n_bands), dim3(row_threads(L)),
+                     lds, st, (const cplx<Real>*)planes, gp, rp, wp, (cplx<Real>*)Tj, code,
+                     (const cplx<Real>*)tw);
   return hipGetLastError();
 }
 
 template <typename Real>
 hipError_t launch_rowpass_accumulate(const void* planes, const GridP& gp, const RadarP& rp,
-                                     const WinP& wp, void* Tj, int32_t* code,
-                                     const RowPlan& pl, const void* tw, hipStream_t st) {
-  hipLaunchKernelGGL(rowpass_accumulate_kernel<Real>, dim3(wp.n_bands), dim3(pl.threads),
-                     pl.acc_bytes, st, (const cplx<Real>*)planes, gp, rp, wp, (cplx<Real>*)Tj,
-                     code, (const cplx<Real>*)tw);
-  return hipGetLastError();
+                                     const WinP& wp, void* Tj, int32_t* code, size_t lds,
+                                     const void* tw, hipStream_t st) {
+  switch (gp.log2nx) {
+#define SIMK_CASE(L) \
+  case L: return rowpass_accumulate_t<Real, L>(planes, gp, rp, wp, Tj, code, lds, tw, st);
+    SIMK_ROW_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename Real>
@@ -600,14 +675,43 @@ hipError_t launch_segments_to_iq(const void* T, void* Y, int G, int N, int log2N
   return hipGetLastError();
 }
 
+// Allow every kernel `lds` bytes of dynamic LDS (the device limit per block).
+template <typename Real>
+static hipError_t set_attributes(int lds) {
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  };
+#define SIMK_CASE(L)                                                                           \
+  if constexpr (col_lds(L, sizeof(cplx<Real>)) <= kLdsBudget)                                  \
+    set((const void*)colpass_kernel<Real, L>);
+  SIMK_COL_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+#define SIMK_CASE(L)                                   \
+  set((const void*)rowpass_facets_kernel<Real, L>);    \
+  set((const void*)rowpass_accumulate_kernel<Real, L>);
+  SIMK_ROW_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+  set((const void*)accumulate_facets_kernel<Real>);
+  set((const void*)reduce_partials_kernel<Real>);
+  set((const void*)segments_to_iq_kernel<Real>);
+  return e;
+}
+
+hipError_t init_kernel_attributes(int lds) {
+  hipError_t e = set_attributes<float>(lds);
+  if (e != hipSuccess) return e;
+  return set_attributes<double>(lds);
+}
+
 #define SIMK_INSTANTIATE(R)                                                                      \
   template hipError_t launch_colpass<R>(const void*, void*, const GridP&, double, double,       \
-                                        const ColPlan&, const void*, hipStream_t);              \
+                                        const void*, hipStream_t);                              \
   template hipError_t launch_rowpass_facets<R>(const void*, const GridP&, void* const*,         \
-                                               const RowPlan&, const void*, hipStream_t);       \
+                                               const void*, hipStream_t);                       \
   template hipError_t launch_rowpass_accumulate<R>(const void*, const GridP&, const RadarP&,     \
-                                                   const WinP&, void*, int32_t*,                \
-                                                   const RowPlan&, const void*, hipStream_t);   \
+                                                   const WinP&, void*, int32_t*, size_t,        \
+                                                   const void*, hipStream_t);                   \
   template hipError_t launch_accumulate_facets<R>(void* const*, const GridP&, const RadarP&,    \
                                                   const WinP&, void*, int32_t*, size_t,         \
                                                   hipStream_t);                                 \

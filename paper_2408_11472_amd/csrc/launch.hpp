@@ -14,14 +14,48 @@ struct FacetPtrs {
   Real* p[9];   // disp_x, disp_y, h, sx, sy, jac, ddisp_x, ddisp_y, dh
 };
 
-// Column pass: CPB columns per block, ny/16 threads per column.
+// Launch geometry shared by the host plans and the kernels (compile time).
+constexpr size_t kLdsBudget = 159 * 1024;   // usable LDS per block
+constexpr int kMinLog2 = 4;                 // grid sides 16 ..
+constexpr int kMaxLog2Col = 13;             // .. 8192 along y
+constexpr int kMaxLog2Row = 12;             // .. 4096 along x
+
+__host__ __device__ constexpr size_t lpad_c(size_t i) { return i + (i >> 4); }
+
+// Column pass: CPB adjacent columns per block, ny/16 threads per column.
+__host__ __device__ constexpr int col_cpb(int log2ny, int cs) {
+  int cpb = 16;
+  while (cpb > 1 && ((long)cpb * ((1 << log2ny) / 16) > 1024 ||
+                     (size_t)cpb * lpad_c((size_t)1 << log2ny) * cs > kLdsBudget))
+    cpb >>= 1;
+  return cpb;
+}
+__host__ __device__ constexpr int col_threads(int log2ny, int cs) {
+  return col_cpb(log2ny, cs) * ((1 << log2ny) / 16);
+}
+__host__ __device__ constexpr size_t col_lds(int log2ny, int cs) {
+  return (size_t)col_cpb(log2ny, cs) * lpad_c((size_t)1 << log2ny) * cs;
+}
+
+// Row passes: ER values per thread, RPB rows per block.
+constexpr int kRowE = 8;
+__host__ __device__ constexpr int row_tpr(int log2nx) { return (1 << log2nx) / kRowE; }
+__host__ __device__ constexpr int row_rpb(int log2nx) {
+  return row_tpr(log2nx) >= 256 ? 1 : 256 / row_tpr(log2nx);
+}
+__host__ __device__ constexpr int row_threads(int log2nx) {
+  return row_rpb(log2nx) * row_tpr(log2nx);
+}
+__host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
+  return (size_t)row_rpb(log2nx) * lpad_c((size_t)1 << log2nx) * cs;
+}
+
 struct ColPlan {
   int cpb;
   int threads;
   size_t lds_bytes;
 };
 
-// Row pass: RPB rows per block, nx/8 threads per row.
 struct RowPlan {
   int rpb;
   int threads;
@@ -33,14 +67,14 @@ hipError_t init_kernel_attributes(int lds_bytes);
 
 template <typename Real>
 hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
-                          const ColPlan& pl, const void* tw, hipStream_t st);
+                          const void* tw, hipStream_t st);
 template <typename Real>
 hipError_t launch_rowpass_facets(const void* planes, const GridP& gp, void* const* out,
-                                 const RowPlan& pl, const void* tw, hipStream_t st);
+                                 const void* tw, hipStream_t st);
 template <typename Real>
 hipError_t launch_rowpass_accumulate(const void* planes, const GridP& gp, const RadarP& rp,
-                                     const WinP& wp, void* Tj, int32_t* code,
-                                     const RowPlan& pl, const void* tw, hipStream_t st);
+                                     const WinP& wp, void* Tj, int32_t* code, size_t lds,
+                                     const void* tw, hipStream_t st);
 template <typename Real>
 hipError_t launch_accumulate_facets(void* const* fac, const GridP& gp, const RadarP& rp,
                                     const WinP& wp, void* Tj, int32_t* code, size_t lds_bytes,
