@@ -30,6 +30,27 @@ METRIC = "facet-updates/s + simulated IQ pulses/s (FP32+FP64-phase vs FP64, same
 # back (48 B) and writes nothing per facet.
 ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48}
 
+# Counter measurements of the FP32 kernels on this workload (profiles/), valid
+# only for the kernel sources they were taken on: HBM bytes per launch from
+# FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), scaled by a 1 GiB copy, and VALU
+# wave-instructions per launch (SQ_INSTS_VALU).
+KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
+MEASURED = {
+    "source_sha": "d57a7c82bc842154",
+    "traffic_bytes": {"surface_colpass": 1434e6, "fused_rowpass": 808e6},
+    "valu_wave_instr": {"surface_colpass": 2.10e8, "fused_rowpass": 1.89e8},
+}
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2408_11472_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -67,17 +88,25 @@ def timed_steps(sim, spec_t, wl, steps, warmup, torch):
     return dt, prof, T, Y
 
 
-def roofline(prof, wl, bytes_scale):
+def roofline(prof, wl, bytes_scale, measured_ok):
     """Dominant kernel against the HBM peak, from its event-timed launches."""
     best = max((k for k in ALG_BYTES_PER_FACET), key=lambda k: prof[k][0])
     ms, n = prof[best]
     avg_s = ms / 1e3 / n
     alg = ALG_BYTES_PER_FACET[best] * bytes_scale * wl.n_facets
     achieved = alg / avg_s / 1e9
-    return {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
-            "alg_bytes_per_launch": alg}
+    out = {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+           "alg_bytes_per_launch": alg}
+    if measured_ok and bytes_scale == 1:
+        out["traffic"] = MEASURED["traffic_bytes"][best]
+        valu = MEASURED["valu_wave_instr"][best]
+        out["valu_issue"] = {"achieved": round(valu / avg_s / 1e9, 1),
+                             "peak": VALU_PEAK_WAVE_INSTR_PER_S / 1e9,
+                             "unit": "G wave-instr/s",
+                             "frac": round(valu / avg_s / VALU_PEAK_WAVE_INSTR_PER_S, 4)}
+    return out
 
 
 def cpu_baseline(spec, wl):
@@ -115,6 +144,7 @@ def main():
     g = wl.grid
     spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh, wl.sea.peak_wavelength,
                                wl.sea.seed, wl.sea.swell)
+    measured_ok = kernel_source_sha() == MEASURED["source_sha"] and a.workload == "track_4096"
     results = {}
     for name, prec, cdt, scale in (("fp32", simradar.SIM_PREC_FP32_PHASE64, np.complex64, 1),
                                    ("fp64", simradar.SIM_PREC_FP64, np.complex128, 2)):
@@ -129,7 +159,7 @@ def main():
             "facet_updates_per_s": wl.n_facets * wl.n_spec * a.steps / dt,
             "iq_pulses_per_s": wl.n_pulses * a.steps / dt,
             "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items() if v[1]},
-            "roofline": roofline(prof, wl, scale),
+            "roofline": roofline(prof, wl, scale, measured_ok),
             "finite": bool(torch.isfinite(torch.view_as_real(Y)).all().item()),
         }
         print(f"[bench] {name}: {ms_step:.2f} ms/step  "
