@@ -17,9 +17,11 @@ the paper is silent, the stated reading) defines it:
                  Algorithm 1, Sec. II.A for the facet radar equation);
 * ``iq``       - batched inverse DFT, eq. (1) weights and overlap-add into the
                  range-azimuth IQ matrix (Sec. III.B post-processing steps 1-4);
-* ``fastmode`` - Algorithm 1 end to end.
+* ``fastmode`` - Algorithm 1 end to end;
+* ``adjoint``  - multi-look waveform, L2 waveform loss and its gradient with
+                 respect to facet heights and slopes (hand adjoint).
 
 Parity status per function is stated in each module header.
 """
 
-from . import surface, scatter, iq, fastmode  # noqa: F401
+from . import surface, scatter, iq, fastmode, adjoint  # noqa: F401

@@ -1,0 +1,96 @@
+"""Pins of the oracle's waveform loss and hand adjoint: the dot-product
+identity of the IQ map and central finite differences of the forward chain."""
+import numpy as np
+import pytest
+
+import oracle.adjoint as oad
+import oracle.iq as oiq
+import oracle.scatter as osc
+import oracle.surface as osurf
+from paper_2408_11472_amd import inputs, workloads
+
+
+@pytest.mark.parametrize("N,n_fast,window", [(16, 16, 0), (32, 8, 1), (8, 12, 0), (64, 16, 0)])
+def test_iq_adjoint_dot_product(N, n_fast, window):
+    rng = np.random.default_rng(N + n_fast)
+    n_spec, G = 5, 3
+    T = inputs.random_spectra(n_spec, G, N, seed=N)
+    Yb = rng.standard_normal(((n_spec - 1) * n_fast, G)) + 1j * rng.standard_normal(((n_spec - 1) * n_fast, G))
+    AT = oiq.segments_to_iq(T, n_fast, window)
+    AhY = oad.segments_to_iq_adjoint(Yb, n_spec, N, n_fast, window)
+    lhs = np.vdot(AT, Yb).real
+    rhs = np.vdot(T, AhY).real
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0)
+
+
+def test_loss_gradient_in_y_by_finite_differences():
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((12, 4)) + 1j * rng.standard_normal((12, 4))
+    target = rng.random(4)
+    Yb = oad.loss_grad_y(Y, target)
+    eps = 1e-6
+    for (x, g) in [(0, 0), (5, 2), (11, 3)]:
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            Yp = Y.copy(); Yp[x, g] += eps * unit
+            Ym = Y.copy(); Ym[x, g] -= eps * unit
+            fd = (oad.loss(oad.waveform(Yp), target) - oad.loss(oad.waveform(Ym), target)) / (2 * eps)
+            an = Yb[x, g].real if part == "re" else Yb[x, g].imag
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def _chain_case():
+    wl = workloads.tiny(nx=16, ny=16, spacing=2.0, n_gates=16, n_doppler=8, n_fast=8,
+                        n_updates=2, seed=31)
+    g, r = wl.grid, wl.radar
+    spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh, wl.sea.peak_wavelength,
+                               wl.sea.seed)
+    times = [wl.update_time(j) for j in range(wl.n_spec)]
+    facs = [osurf.facets(spec, g, t, 1.0 / r.prf_hz) for t in times]
+    rng = np.random.default_rng(5)
+    target = rng.random(r.n_gates) * 10.0
+    return wl, facs, times, target
+
+
+def _margin_ok(fac, wl, t, iy, ix):
+    dx, dy, dz, r, r2 = osc.pulse_pair_ranges(fac, wl.grid, wl.radar, t)
+    xi = osc.gate_coordinate(r, wl.radar)[iy, ix]
+    u = osc.doppler_cycles(r, r2, wl.radar)[iy, ix] * wl.radar.n_doppler
+    return abs(xi - round(xi)) > 1e-3 and abs(u + 0.5 - round(u + 0.5)) > 1e-3
+
+
+# The facet-to-satellite range (~815 km) carries a 1.2e-10 m rounding floor in
+# float64, so the height step must stay well above it: h uses a fourth-order
+# central stencil with a 2e-5 m step (truncation ~1e-9, rounding ~6e-6); the
+# slopes use the second-order stencil with a 1e-6 step.
+@pytest.mark.parametrize("field,eps,tol", [("h", 2e-5, 3e-5), ("sx", 1e-6, 1e-6),
+                                           ("sy", 1e-6, 1e-6)])
+def test_chain_gradient_by_central_differences(field, eps, tol):
+    wl, facs, times, target = _chain_case()
+    L0, grads = oad.gradients(facs, times, wl.grid, wl.radar, target)
+    rng = np.random.default_rng(11)
+    checked = 0
+    for _ in range(40):
+        j = int(rng.integers(0, len(facs)))
+        iy, ix = int(rng.integers(0, 16)), int(rng.integers(0, 16))
+        code = osc.scatterers(facs[j], wl.grid, wl.radar, times[j])[0]
+        if code[iy, ix] < 0 or not _margin_ok(facs[j], wl, times[j], iy, ix):
+            continue
+        def L_at(delta):
+            fs = [dict(f) for f in facs]
+            fs[j][field] = facs[j][field].copy()
+            fs[j][field][iy, ix] += delta
+            return oad.forward_loss(fs, times, wl.grid, wl.radar, target)[0]
+
+        if field == "h":
+            fd = (8 * (L_at(eps) - L_at(-eps)) - (L_at(2 * eps) - L_at(-2 * eps))) / (12 * eps)
+        else:
+            fd = (L_at(eps) - L_at(-eps)) / (2 * eps)
+        an = grads[j][field][iy, ix]
+        floor = 8 * abs(L0) * 2.2e-16 / eps      # rounding floor of the difference quotient
+        if abs(an) < 1e3 * floor:
+            continue                              # gradient too small to resolve by differences
+        assert abs(fd - an) <= tol * abs(an) + floor, (j, iy, ix, fd, an)
+        checked += 1
+        if checked == 12:
+            break
+    assert checked >= 8
