@@ -30,7 +30,8 @@
  *    range, gate, Doppler bin and carrier phase are nevertheless computed in
  *    double on the GPU (4 pi R / lambda at ~815 km in Ku band has no phase
  *    left in float).
- *  - Grid sides are powers of two: 16 <= nx <= 4096, 16 <= ny <= 8192.
+ *  - Grid sides are powers of two: 16 <= nx <= 8192, 16 <= ny <= 16384
+ *    (ny <= 8192 in FP64).
  *    Doppler bins n_doppler: power of two, 2 <= n_doppler <= 2048.
  *  - Calls that run concurrently on one context race on its workspace.
  */
@@ -212,6 +213,80 @@ sim_status sim_segments_to_iq(sim_ctx *ctx, const sim_radar *radar,
                               const void *t_fast, int32_t n_spec, void *y,
                               void *stream);
 
+/* ---- differentiable chain ------------------------------------------------
+ * Gradients of a multi-look waveform loss (the echoes are multi-looked before
+ * retracking in Sec. IV.B; the inversion of sea-state parameters motivates
+ * the gradient, Sec. V) with respect to the facet heights and slopes of every
+ * update.  Gate and bin indices are piecewise constant and get no gradient;
+ * the other facet fields are held fixed.  Complex gradients follow the
+ * convention dL/dRe + i dL/dIm.  Reals are float or double by context. */
+
+/* p[g] = (1/n_pulses) sum_x |y[x][g]|^2 (written); when loss != NULL also
+ * loss[0] = sum_g (p[g] - target[g])^2 (target [n_gates], read only).
+ *   y  [n_pulses][n_gates] complex. */
+sim_status sim_waveform_loss(sim_ctx *ctx, const sim_radar *radar, const void *y,
+                             int32_t n_pulses, const void *target, void *p, void *loss,
+                             void *stream);
+
+/* y_bar[x][g] = s * 2 (p[g] - target[g]) * 2 y[x][g] / n_pulses, the gradient
+ * of the loss above times s = scale[0] (a device scalar; NULL means 1). */
+sim_status sim_waveform_loss_adjoint(sim_ctx *ctx, const sim_radar *radar, const void *y,
+                                     int32_t n_pulses, const void *p, const void *target,
+                                     const void *scale, void *y_bar, void *stream);
+
+/* Adjoint of sim_segments_to_iq:
+ * t_fast_bar[j][g][k] = sum_x W(x - j n_fast) y_bar[x][g]
+ *                       exp(-2 pi i k ((x - j n_fast) mod N) / N)
+ * over the pulses x in [0, (n_spec - 1) n_fast) with |x - j n_fast| < n_fast.
+ * Written, [n_spec][n_gates][n_doppler] complex. */
+sim_status sim_segments_to_iq_adjoint(sim_ctx *ctx, const sim_radar *radar, const void *y_bar,
+                                      int32_t n_spec, void *t_fast_bar, void *stream);
+
+/* Adjoint of sim_range_doppler_accumulate for update j: every illuminated
+ * facet's scatterer is recomputed from `facets` (nothing was stored) and
+ *   grad_theta = Re(conj(t_fast_bar[j][g][bin]) dC/dtheta), theta = h, sx, sy;
+ * dropped facets get 0.  grad_h, grad_sx, grad_sy: [ny][nx] real, written. */
+sim_status sim_range_doppler_accumulate_adjoint(sim_ctx *ctx, const sim_grid *grid,
+                                                const sim_facets *facets,
+                                                const sim_radar *radar, double t, int32_t j,
+                                                const void *t_fast_bar, int32_t n_spec,
+                                                void *grad_h, void *grad_sx, void *grad_sy,
+                                                void *stream);
+
+/* ---- batches of independent realisations --------------------------------
+ * The paper averages spectra over ~100 realisations of the acquisition
+ * (Sec. I, Sec. IV.D).  A batch holds R realisations with their own grid
+ * (sides may differ), radar and update count; running it performs Algorithm 1
+ * and the post-processing for every realisation, update-major
+ * (update j of every realisation, then j + 1), on one stream.  The work can be
+ * captured once into a HIP graph and replayed with a single launch per run.
+ * The context's workspace must cover the largest realisation
+ * (sim_batch_workspace_size).  Per-realisation buffers are given as arrays of
+ * device pointers (host arrays of R entries):
+ *   spec0[r]   [ny_r][nx_r] complex spectrum
+ *   t_fast[r]  [n_updates_r + 1][G_r][N_r] complex, cleared by the run
+ *   y[r]       [n_updates_r n_fast_r][G_r] complex, written (NULL: skip IQ) */
+typedef struct sim_batch sim_batch;
+
+sim_status sim_batch_create(sim_ctx *ctx, int32_t n_real, const sim_grid *grids,
+                            const sim_radar *radars, const int32_t *n_updates,
+                            sim_batch **batch);
+sim_status sim_batch_destroy(sim_batch *batch);
+sim_status sim_batch_workspace_size(const sim_batch *batch, size_t *bytes);
+
+/* Enqueue the whole batch on `stream`.  use_graph != 0: the first call with a
+ * given set of pointers captures the launches into a graph on `stream`
+ * (which must not be the NULL stream), later calls with the same pointers
+ * replay it; a call with other pointers captures again. */
+sim_status sim_batch_run(sim_batch *batch, void *const *spec0, void *const *t_fast,
+                         void *const *y, int use_graph, void *stream);
+
+/* ---- tuning ---------------------------------------------------------------
+ * Launch parameters that do not change results beyond summation order;
+ * bench/autotune code sets them per context. */
+#define SIM_TUNE_ROW_BANDS 0      /* blocks of the fused row pass (bands of rows), 0 = default */
+sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
+
 /* ---- per-kernel timing (profiling aid) ----------------------------------
  * While enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the stream it is launched on; sim_profile_read waits
@@ -223,7 +298,9 @@ sim_status sim_segments_to_iq(sim_ctx *ctx, const sim_radar *radar,
 #define SIM_KERNEL_ACCUMULATE_FACETS 3    /* facet SoA -> scatterers + windows   */
 #define SIM_KERNEL_REDUCE_PARTIALS 4      /* windows -> T_fast[j]                */
 #define SIM_KERNEL_SEGMENTS_TO_IQ 5       /* T_fast -> Y                         */
-#define SIM_KERNEL_KINDS 6
+#define SIM_KERNEL_ADJOINT 6              /* waveform loss and adjoint kernels   */
+#define SIM_KERNEL_CLEAR 7                /* clearing T_fast in a batch run      */
+#define SIM_KERNEL_KINDS 8
 
 typedef struct sim_kernel_times {
   double ms[SIM_KERNEL_KINDS];

@@ -25,6 +25,8 @@ struct sim_ctx {
   void* tw;            // kTwSize complex, precision of the context
   void* ws;
   size_t ws_bytes;
+  int row_bands;   // tuning: bands of the fused row pass (0 = default)
+  bool capturing;  // a batch is being captured into a graph
   // per-kernel timing
   bool profiling;
   std::vector<hipEvent_t> ev;   // pool, pairs (start, stop)
@@ -59,7 +61,8 @@ size_t csize(const sim_ctx* c) { return c->prec == SIM_PREC_FP64 ? 16 : 8; }
 sim_status check_grid(const sim_ctx* c, const sim_grid* g) {
   if (!g) return SIM_ERR_ARG;
   if (!is_pow2(g->nx) || !is_pow2(g->ny)) return SIM_ERR_UNSUPPORTED;
-  if (g->nx < 16 || g->nx > 4096 || g->ny < 16 || g->ny > 8192) return SIM_ERR_UNSUPPORTED;
+  if (g->nx < 16 || g->nx > 8192 || g->ny < 16 || g->ny > 16384) return SIM_ERR_UNSUPPORTED;
+  if (c->prec == SIM_PREC_FP64 && g->ny > 8192) return SIM_ERR_UNSUPPORTED;
   if (!(isfin(g->dx) && g->dx > 0 && isfin(g->dy) && g->dy > 0)) return SIM_ERR_ARG;
   if (!(isfin(g->x_origin) && isfin(g->y_origin))) return SIM_ERR_ARG;
   if (!(isfin(g->gravity) && g->gravity > 0)) return SIM_ERR_ARG;
@@ -255,7 +258,8 @@ struct ProfScope {
   sim_ctx* c;
   hipStream_t st;
   bool on;
-  ProfScope(sim_ctx* c_, int kind, hipStream_t st_) : c(c_), st(st_), on(c_->profiling) {
+  ProfScope(sim_ctx* c_, int kind, hipStream_t st_)
+      : c(c_), st(st_), on(c_->profiling && !c_->capturing) {
     if (!on) return;
     if (c->used * 2 + 2 > c->ev.size()) {
       hipEvent_t a, b;
@@ -294,7 +298,8 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, rpl.fft_bytes);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
   rpl.acc_bytes = rpl.fft_bytes + (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
-  const int target = rpl.threads <= 512 ? kMaxBands : kMaxBands / 2;
+  int target = rpl.threads <= 512 ? kMaxBands : kMaxBands / 2;
+  if (c->row_bands > 0 && c->row_bands < target) target = c->row_bands;
   int n_bands, band_rows;
   if (g->ny >= rpl.rpb) {
     n_bands = g->ny / rpl.rpb < target ? g->ny / rpl.rpb : target;
@@ -398,6 +403,8 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->tw = nullptr;
   c->profiling = false;
   c->used = 0;
+  c->row_bands = 0;
+  c->capturing = false;
   const size_t cs = csize(c);
   const size_t bytes = (size_t)simk::kTwEntries * cs;
   if (dev(hipMalloc(&c->tw, bytes)) != SIM_OK) {
@@ -561,6 +568,111 @@ sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* 
                                                 ctx->tw, st));
 }
 
+sim_status sim_waveform_loss(sim_ctx* ctx, const sim_radar* radar, const void* y,
+                             int32_t n_pulses, const void* target, void* p, void* loss,
+                             void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!y || !p || (loss && !target)) return SIM_ERR_ARG;
+  if (n_pulses < 1) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope pf(ctx, SIM_KERNEL_ADJOINT, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_waveform_loss<double>(y, n_pulses, radar->n_gates, target, p, loss, st));
+  return dev(simk::launch_waveform_loss<float>(y, n_pulses, radar->n_gates, target, p, loss, st));
+}
+
+sim_status sim_waveform_loss_adjoint(sim_ctx* ctx, const sim_radar* radar, const void* y,
+                                     int32_t n_pulses, const void* p, const void* target,
+                                     const void* scale, void* y_bar, void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!y || !p || !target || !y_bar) return SIM_ERR_ARG;
+  if (n_pulses < 1) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope pf(ctx, SIM_KERNEL_ADJOINT, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_waveform_loss_adjoint<double>(y, p, target, scale, n_pulses,
+                                                          radar->n_gates, y_bar, st));
+  return dev(simk::launch_waveform_loss_adjoint<float>(y, p, target, scale, n_pulses,
+                                                       radar->n_gates, y_bar, st));
+}
+
+sim_status sim_segments_to_iq_adjoint(sim_ctx* ctx, const sim_radar* radar, const void* y_bar,
+                                      int32_t n_spec, void* t_fast_bar, void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!y_bar || !t_fast_bar) return SIM_ERR_ARG;
+  if (n_spec < 2) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  const size_t cs = csize(ctx);
+  const int N = radar->n_doppler;
+  long gb = (long)(kLdsBudget / (2 * (size_t)N * cs));
+  if (gb < 1) return SIM_ERR_UNSUPPORTED;
+  if (gb > 64) gb = 64;
+  if (gb > radar->n_gates) gb = radar->n_gates;
+  const int n_pulses = (n_spec - 1) * radar->n_fast;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope pf(ctx, SIM_KERNEL_ADJOINT, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_segments_to_iq_adjoint<double>(y_bar, t_fast_bar, radar->n_gates, N,
+                                                           radar->n_fast, n_pulses, radar->window,
+                                                           n_spec, (int)gb, ctx->tw, st));
+  return dev(simk::launch_segments_to_iq_adjoint<float>(y_bar, t_fast_bar, radar->n_gates, N,
+                                                        radar->n_fast, n_pulses, radar->window,
+                                                        n_spec, (int)gb, ctx->tw, st));
+}
+
+sim_status sim_range_doppler_accumulate_adjoint(sim_ctx* ctx, const sim_grid* grid,
+                                                const sim_facets* facets,
+                                                const sim_radar* radar, double t, int32_t j,
+                                                const void* t_fast_bar, int32_t n_spec,
+                                                void* grad_h, void* grad_sx, void* grad_sy,
+                                                void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!facets_ok(facets) || !t_fast_bar || !grad_h || !grad_sx || !grad_sy || !isfin(t))
+    return SIM_ERR_ARG;
+  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  GridP gp;
+  RadarP rp;
+  fill_grid(grid, gp);
+  fill_radar(radar, grid, t, rp);
+  void* const fp[9] = {facets->disp_x, facets->disp_y, facets->h, facets->sx, facets->sy,
+                       facets->jac, facets->ddisp_x, facets->ddisp_y, facets->dh};
+  const size_t cs = csize(ctx);
+  const void* Tj = (const char*)t_fast_bar + (size_t)j * radar->n_gates * radar->n_doppler * cs;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope pf(ctx, SIM_KERNEL_ADJOINT, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_accumulate_adjoint<double>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy,
+                                                       st));
+  return dev(simk::launch_accumulate_adjoint<float>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy, st));
+}
+
+sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
+  if (!ctx) return SIM_ERR_ARG;
+  if (key == SIM_TUNE_ROW_BANDS) {
+    if (value < 0 || value > kMaxBands || (value & (value - 1)) != 0) return SIM_ERR_ARG;
+    ctx->row_bands = value;
+    return SIM_OK;
+  }
+  return SIM_ERR_ARG;
+}
+
 sim_status sim_profile_enable(sim_ctx* ctx, int enable) {
   if (!ctx) return SIM_ERR_ARG;
   ctx->profiling = enable != 0;
@@ -587,6 +699,156 @@ sim_status sim_profile_read(sim_ctx* ctx, sim_kernel_times* out) {
     out->launches[ctx->kind[i]] += 1;
   }
   return SIM_OK;
+}
+
+}  // extern "C"
+
+struct sim_batch {
+  sim_ctx* ctx;
+  std::vector<sim_grid> grids;
+  std::vector<sim_radar> radars;
+  std::vector<int32_t> updates;
+  size_t ws_bytes;
+  // captured graph and the pointers it was captured with
+  hipGraphExec_t exec;
+  bool have_graph;
+  std::vector<void*> key;
+  hipStream_t graph_stream;
+};
+
+namespace {
+
+sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, void* const* y,
+                         hipStream_t st) {
+  sim_ctx* c = b->ctx;
+  const int R = (int)b->grids.size();
+  const size_t cs = csize(c);
+  int jmax = 0;
+  for (int r = 0; r < R; ++r) jmax = b->updates[r] > jmax ? b->updates[r] : jmax;
+  for (int r = 0; r < R; ++r) {
+    const sim_radar& rr = b->radars[r];
+    const size_t n = (size_t)(b->updates[r] + 1) * rr.n_gates * rr.n_doppler;
+    ProfScope p(c, SIM_KERNEL_CLEAR, st);
+    const sim_status s = dev(simk::launch_clear(t_fast[r], n * cs, st));
+    if (s != SIM_OK) return s;
+  }
+  for (int j = 0; j <= jmax; ++j) {
+    for (int r = 0; r < R; ++r) {
+      if (j > b->updates[r]) continue;
+      const sim_radar& rr = b->radars[r];
+      const double t = ((double)j * rr.n_fast) / rr.prf_hz;
+      const sim_status s = sim_update_and_accumulate(c, &b->grids[r], spec0[r], &rr, t, j,
+                                                     t_fast[r], b->updates[r] + 1, nullptr,
+                                                     nullptr, st);
+      if (s != SIM_OK) return s;
+    }
+  }
+  if (y) {
+    for (int r = 0; r < R; ++r) {
+      if (!y[r]) continue;
+      const sim_status s = sim_segments_to_iq(c, &b->radars[r], t_fast[r], b->updates[r] + 1,
+                                              y[r], st);
+      if (s != SIM_OK) return s;
+    }
+  }
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
+                            const sim_radar* radars, const int32_t* n_updates,
+                            sim_batch** batch) {
+  if (!batch) return SIM_ERR_ARG;
+  *batch = nullptr;
+  if (!ctx || n_real < 1 || !grids || !radars || !n_updates) return SIM_ERR_ARG;
+  size_t ws = 0;
+  for (int r = 0; r < n_real; ++r) {
+    sim_status s = check_grid(ctx, &grids[r]);
+    if (s != SIM_OK) return s;
+    s = check_radar(&radars[r]);
+    if (s != SIM_OK) return s;
+    if (n_updates[r] < 1) return SIM_ERR_SHAPE;
+    if (window_bins(radars[r].n_gates, radars[r].n_doppler, csize(ctx), 0) < 1)
+      return SIM_ERR_UNSUPPORTED;
+    const size_t need = ws_layout(&grids[r], &radars[r], csize(ctx)).total;
+    ws = need > ws ? need : ws;
+  }
+  sim_batch* b = new (std::nothrow) sim_batch;
+  if (!b) return SIM_ERR_DEVICE;
+  b->ctx = ctx;
+  b->grids.assign(grids, grids + n_real);
+  b->radars.assign(radars, radars + n_real);
+  b->updates.assign(n_updates, n_updates + n_real);
+  b->ws_bytes = ws;
+  b->have_graph = false;
+  b->graph_stream = nullptr;
+  *batch = b;
+  return SIM_OK;
+}
+
+sim_status sim_batch_destroy(sim_batch* b) {
+  if (!b) return SIM_OK;
+  sim_status s = SIM_OK;
+  if (b->have_graph && hipGraphExecDestroy(b->exec) != hipSuccess) s = SIM_ERR_DEVICE;
+  delete b;
+  return s;
+}
+
+sim_status sim_batch_workspace_size(const sim_batch* b, size_t* bytes) {
+  if (!b || !bytes) return SIM_ERR_ARG;
+  *bytes = b->ws_bytes;
+  return SIM_OK;
+}
+
+sim_status sim_batch_run(sim_batch* b, void* const* spec0, void* const* t_fast, void* const* y,
+                         int use_graph, void* stream) {
+  if (!b || !spec0 || !t_fast) return SIM_ERR_ARG;
+  const int R = (int)b->grids.size();
+  for (int r = 0; r < R; ++r)
+    if (!spec0[r] || !t_fast[r]) return SIM_ERR_ARG;
+  sim_ctx* c = b->ctx;
+  if (!c->ws) return SIM_ERR_WORKSPACE;
+  if (c->ws_bytes < b->ws_bytes) return SIM_ERR_WORKSPACE;
+  sim_status s = use_device(c);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) return batch_enqueue(b, spec0, t_fast, y, st);
+  if (!st) return SIM_ERR_ARG;
+  std::vector<void*> key;
+  key.push_back(c->ws);
+  for (int r = 0; r < R; ++r) {
+    key.push_back(spec0[r]);
+    key.push_back(t_fast[r]);
+    key.push_back(y ? y[r] : nullptr);
+  }
+  if (!b->have_graph || key != b->key || b->graph_stream != st) {
+    if (b->have_graph) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->have_graph = false;
+    }
+    s = dev(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    if (s != SIM_OK) return s;
+    c->capturing = true;
+    const sim_status se = batch_enqueue(b, spec0, t_fast, y, st);
+    c->capturing = false;
+    hipGraph_t graph;
+    s = dev(hipStreamEndCapture(st, &graph));
+    if (se != SIM_OK) {
+      if (s == SIM_OK) (void)hipGraphDestroy(graph);
+      return se;
+    }
+    if (s != SIM_OK) return s;
+    s = dev(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    if (s != SIM_OK) return s;
+    b->have_graph = true;
+    b->key = key;
+    b->graph_stream = st;
+  }
+  return dev(hipGraphLaunch(b->exec, st));
 }
 
 }  // extern "C"

@@ -560,11 +560,169 @@ segments_to_iq_kernel(const cplx<Real>* __restrict__ T, cplx<Real>* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Differentiable chain (adjoint of rasterisation and post-processing).
+
+// P[g] = mean_x |Y[x][g]|^2 over the run.  Block = 64 gates x 4 pulse lanes;
+// each lane sums its pulses in order (double), lanes are added in order.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+waveform_kernel(const cplx<Real>* __restrict__ Y, int n_pulses, int G, Real* __restrict__ P) {
+  __shared__ double part[4][64];
+  const int gl = threadIdx.x & 63, xl = threadIdx.x >> 6;
+  const int g = blockIdx.x * 64 + gl;
+  double acc = 0.0;
+  if (g < G) {
+    for (int x = xl; x < n_pulses; x += 4) {
+      const cplx<Real> y = Y[(size_t)x * G + g];
+      acc += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+    }
+  }
+  part[xl][gl] = acc;
+  __syncthreads();
+  if (xl == 0 && g < G)
+    P[g] = (Real)((((part[0][gl] + part[1][gl]) + part[2][gl]) + part[3][gl]) / (double)n_pulses);
+}
+
+// loss = sum_g (P[g] - target[g])^2, one block, fixed summation order.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+waveform_loss_kernel(const Real* __restrict__ P, const Real* __restrict__ target, int G,
+                     Real* __restrict__ loss) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const double d = (double)P[g] - (double)target[g];
+    acc += d * d;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = (Real)part[0];
+}
+
+// Y_bar[x][g] = s * 2 (P[g] - target[g]) * 2 Y[x][g] / n_pulses, s = *scale (or 1).
+template <typename Real>
+__global__ void __launch_bounds__(256)
+waveform_loss_adjoint_kernel(const cplx<Real>* __restrict__ Y, const Real* __restrict__ P,
+                             const Real* __restrict__ target, const Real* __restrict__ scale,
+                             int n_pulses, int G, cplx<Real>* __restrict__ Ybar) {
+  const size_t n = (size_t)n_pulses * G;
+  const Real s = scale ? scale[0] : (Real)1;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int g = (int)(i % G);
+    const Real f = s * (Real)4 * (P[g] - target[g]) / (Real)n_pulses;
+    Ybar[i] = cscale(Y[i], f);
+  }
+}
+
+// T_bar[j][g][k] = sum_x W(x - c_j) Y_bar[x][g] e^{-2 pi i k ((x - c_j) mod N) / N}:
+// the windowed pulses of segment j are folded modulo N (in increasing x per
+// bin) and forward transformed in LDS (radix-2 Stockham, ping-pong).
+template <typename Real>
+__global__ void __launch_bounds__(256)
+segments_to_iq_adjoint_kernel(const cplx<Real>* __restrict__ Ybar, cplx<Real>* __restrict__ Tbar,
+                              int G, int N, int n_fast, int n_pulses, int window, int GB,
+                              const cplx<Real>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<Real>* bufA = reinterpret_cast<cplx<Real>*>(smem_raw);
+  cplx<Real>* bufB = bufA + (size_t)GB * N;
+  const int g0 = blockIdx.x * GB;
+  const int j = blockIdx.y;
+  const int c = j * n_fast;
+  for (int i = threadIdx.x; i < GB * N; i += blockDim.x) {
+    const int gl = i % GB, m = i / GB;
+    const int g = g0 + gl;
+    double ax = 0.0, ay = 0.0;
+    if (g < G) {
+      // smallest d > -n_fast with d = m (mod N), then every N up to n_fast - 1
+      int d = m - N * ((m + n_fast - 1) / N);
+      for (; d < n_fast; d += N) {
+        const int x = c + d;
+        if (x < 0 || x >= n_pulses) continue;
+        const int ad = d < 0 ? -d : d;
+        const double w = window == 0 ? __builtin_sqrt((double)(n_fast - ad) / (double)n_fast)
+                                     : cos(1.5707963267948966192 * ((double)d / (double)n_fast));
+        const cplx<Real> y = Ybar[(size_t)x * G + g];
+        ax += w * (double)y.x;
+        ay += w * (double)y.y;
+      }
+    }
+    bufA[(size_t)gl * N + m] = mk<Real>((Real)ax, (Real)ay);
+  }
+  __syncthreads();
+  cplx<Real>* src = bufA;
+  cplx<Real>* dst = bufB;
+  const int half = N / 2;
+  for (int Ns = 1; Ns < N; Ns <<= 1) {
+    for (int i = threadIdx.x; i < GB * half; i += blockDim.x) {
+      const int sq = i / half, b = i - sq * half;
+      const int jb = b & (Ns - 1);
+      const cplx<Real>* in = src + (size_t)sq * N;
+      cplx<Real>* out = dst + (size_t)sq * N;
+      const cplx<Real> a = in[b];
+      const cplx<Real> w = cconj(tw[2 * Ns + jb]);
+      const cplx<Real> cc = cmul(in[b + half], w);
+      const int o = (b - jb) * 2 + jb;
+      out[o] = cadd(a, cc);
+      out[o + Ns] = csub(a, cc);
+    }
+    __syncthreads();
+    cplx<Real>* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  for (int i = threadIdx.x; i < GB * N; i += blockDim.x) {
+    const int gl = i / N, k = i - gl * N;
+    const int g = g0 + gl;
+    if (g < G) Tbar[((size_t)j * G + g) * N + k] = src[i];
+  }
+}
+
+// Per-facet gradients of one update: the scatterer and its indices are
+// recomputed, C_bar = T_bar[j][g][bin] is gathered and
+// dL/dtheta = Re(conj(C_bar) C (d ln a/dtheta + i d phi/dtheta)).
+template <typename Real>
+__global__ void __launch_bounds__(256)
+accumulate_adjoint_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp,
+                          const cplx<Real>* __restrict__ Tbar_j, Real* __restrict__ gh,
+                          Real* __restrict__ gsx, Real* __restrict__ gsy) {
+  const size_t nfac = (size_t)gp.nx * gp.ny;
+  for (size_t f = blockIdx.x * (size_t)blockDim.x + threadIdx.x; f < nfac;
+       f += (size_t)gridDim.x * blockDim.x) {
+    const int iy = (int)(f >> gp.log2nx);
+    const int ix = (int)(f & (size_t)(gp.nx - 1));
+    const Real Dx = fac.p[0][f], Dy = fac.p[1][f], h = fac.p[2][f], sx = fac.p[3][f],
+               sy = fac.p[4][f];
+    cplx<Real> C;
+    const int key = scatterer<Real>(rp, gp, ix, iy, Dx, Dy, h, sx, sy, fac.p[5][f], fac.p[6][f],
+                                    fac.p[7][f], fac.p[8][f], C);
+    Real a = 0, b = 0, cgrad = 0;
+    if (key >= 0) {
+      const cplx<Real> Cb = Tbar_j[key];   // key = g N + bin indexes [G][N]
+      const FacetDeriv D = facet_derivatives<Real>(rp, gp, ix, iy, Dx, Dy, h, sx, sy);
+      // Re(conj(Cb) C (l + i p)) = Re(conj(Cb) C) l - Im(conj(Cb) C) p
+      const double re = (double)Cb.x * (double)C.x + (double)Cb.y * (double)C.y;
+      const double im = (double)Cb.x * (double)C.y - (double)Cb.y * (double)C.x;
+      a = (Real)(re * D.lnh - im * D.phih);
+      b = (Real)(re * D.lnsx);
+      cgrad = (Real)(re * D.lnsy);
+    }
+    gh[f] = a;
+    gsx[f] = b;
+    gsy[f] = cgrad;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launch wrappers.  The FFT kernels are instantiated for every
 // supported power-of-two side and selected here by log2 of the side.
 
-#define SIMK_COL_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
-#define SIMK_ROW_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+#define SIMK_COL_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+#define SIMK_ROW_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
 
 template <typename Real, int L>
 static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, double t, double dt,
@@ -675,6 +833,74 @@ hipError_t launch_segments_to_iq(const void* T, void* Y, int G, int N, int log2N
   return hipGetLastError();
 }
 
+template <typename Real>
+hipError_t launch_waveform_loss(const void* Y, int n_pulses, int G, const void* target, void* P,
+                                void* loss, hipStream_t st) {
+  hipLaunchKernelGGL(waveform_kernel<Real>, dim3((G + 63) / 64), dim3(256), 0, st,
+                     (const cplx<Real>*)Y, n_pulses, G, (Real*)P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !loss) return e;
+  hipLaunchKernelGGL(waveform_loss_kernel<Real>, dim3(1), dim3(256), 0, st, (const Real*)P,
+                     (const Real*)target, G, (Real*)loss);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_waveform_loss_adjoint(const void* Y, const void* P, const void* target,
+                                        const void* scale, int n_pulses, int G, void* Ybar,
+                                        hipStream_t st) {
+  const size_t n = (size_t)n_pulses * G;
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL(waveform_loss_adjoint_kernel<Real>, dim3(blocks), dim3(256), 0, st,
+                     (const cplx<Real>*)Y, (const Real*)P, (const Real*)target,
+                     (const Real*)scale, n_pulses, G, (cplx<Real>*)Ybar);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_segments_to_iq_adjoint(const void* Ybar, void* Tbar, int G, int N, int n_fast,
+                                         int n_pulses, int window, int n_spec, int GB,
+                                         const void* tw, hipStream_t st) {
+  const size_t lds = (size_t)2 * GB * N * sizeof(cplx<Real>);
+  hipLaunchKernelGGL(segments_to_iq_adjoint_kernel<Real>, dim3((G + GB - 1) / GB, n_spec),
+                     dim3(256), lds, st, (const cplx<Real>*)Ybar, (cplx<Real>*)Tbar, G, N, n_fast,
+                     n_pulses, window, GB, (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_accumulate_adjoint(void* const* fac, const GridP& gp, const RadarP& rp,
+                                     const void* Tbar_j, void* gh, void* gsx, void* gsy,
+                                     hipStream_t st) {
+  FacetPtrs<Real> fp;
+  for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)fac[i];
+  const size_t n = (size_t)gp.nx * gp.ny;
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL(accumulate_adjoint_kernel<Real>, dim3(blocks), dim3(256), 0, st, fp, gp, rp,
+                     (const cplx<Real>*)Tbar_j, (Real*)gh, (Real*)gsx, (Real*)gsy);
+  return hipGetLastError();
+}
+
+// Zero a buffer with a kernel (no memset node when captured into a graph).
+__global__ void __launch_bounds__(256) clear_kernel(uint4* __restrict__ p, size_t n16,
+                                                    unsigned char* __restrict__ tail, int ntail) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_clear(void* p, size_t bytes, hipStream_t st) {
+  const size_t n16 = bytes / 16;
+  const int ntail = (int)(bytes - n16 * 16);
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)p, n16,
+                     (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
 // Allow every kernel `lds` bytes of dynamic LDS (the device limit per block).
 template <typename Real>
 static hipError_t set_attributes(int lds) {
@@ -695,6 +921,7 @@ static hipError_t set_attributes(int lds) {
   set((const void*)accumulate_facets_kernel<Real>);
   set((const void*)reduce_partials_kernel<Real>);
   set((const void*)segments_to_iq_kernel<Real>);
+  set((const void*)segments_to_iq_adjoint_kernel<Real>);
   return e;
 }
 
@@ -718,7 +945,15 @@ hipError_t init_kernel_attributes(int lds) {
   template hipError_t launch_reduce<R>(const RadarP&, const WinP&, void*, unsigned long long*,  \
                                        hipStream_t);                                            \
   template hipError_t launch_segments_to_iq<R>(const void*, void*, int, int, int, int, int, int, \
-                                               int, const void*, hipStream_t);
+                                               int, const void*, hipStream_t);                  \
+  template hipError_t launch_waveform_loss<R>(const void*, int, int, const void*, void*, void*, \
+                                              hipStream_t);                                     \
+  template hipError_t launch_waveform_loss_adjoint<R>(const void*, const void*, const void*,    \
+                                                      const void*, int, int, void*, hipStream_t); \
+  template hipError_t launch_segments_to_iq_adjoint<R>(const void*, void*, int, int, int, int,  \
+                                                       int, int, int, const void*, hipStream_t); \
+  template hipError_t launch_accumulate_adjoint<R>(void* const*, const GridP&, const RadarP&,   \
+                                                   const void*, void*, void*, void*, hipStream_t);
 
 SIMK_INSTANTIATE(float)
 SIMK_INSTANTIATE(double)

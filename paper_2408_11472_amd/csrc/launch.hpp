@@ -17,8 +17,8 @@ struct FacetPtrs {
 // Launch geometry shared by the host plans and the kernels (compile time).
 constexpr size_t kLdsBudget = 159 * 1024;   // usable LDS per block
 constexpr int kMinLog2 = 4;                 // grid sides 16 ..
-constexpr int kMaxLog2Col = 13;             // .. 8192 along y
-constexpr int kMaxLog2Row = 12;             // .. 4096 along x
+constexpr int kMaxLog2Col = 14;             // .. 16384 along y (8192 in double)
+constexpr int kMaxLog2Row = 13;             // .. 8192 along x
 
 __host__ __device__ constexpr size_t lpad_c(size_t i) { return i + (i >> 4); }
 
@@ -64,6 +64,7 @@ struct RowPlan {
 };
 
 hipError_t init_kernel_attributes(int lds_bytes);
+hipError_t launch_clear(void* p, size_t bytes, hipStream_t st);
 
 template <typename Real>
 hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
@@ -85,5 +86,21 @@ hipError_t launch_reduce(const RadarP& rp, const WinP& wp, void* Tj, unsigned lo
 template <typename Real>
 hipError_t launch_segments_to_iq(const void* T, void* Y, int G, int N, int log2N, int n_fast,
                                  int window, int n_seg, int GB, const void* tw, hipStream_t st);
+
+template <typename Real>
+hipError_t launch_waveform_loss(const void* Y, int n_pulses, int G, const void* target, void* P,
+                                void* loss, hipStream_t st);
+template <typename Real>
+hipError_t launch_waveform_loss_adjoint(const void* Y, const void* P, const void* target,
+                                        const void* scale, int n_pulses, int G, void* Ybar,
+                                        hipStream_t st);
+template <typename Real>
+hipError_t launch_segments_to_iq_adjoint(const void* Ybar, void* Tbar, int G, int N, int n_fast,
+                                         int n_pulses, int window, int n_spec, int GB,
+                                         const void* tw, hipStream_t st);
+template <typename Real>
+hipError_t launch_accumulate_adjoint(void* const* fac, const GridP& gp, const RadarP& rp,
+                                     const void* Tbar_j, void* gh, void* gsx, void* gsy,
+                                     hipStream_t st);
 
 }  // namespace simk

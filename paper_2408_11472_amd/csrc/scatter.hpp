@@ -312,3 +312,54 @@ __device__ __forceinline__ void count_code(int code, uint32_t* c) {
 }
 
 }  // namespace simk
+
+namespace simk {
+
+// Derivatives of the scatterer of one illuminated facet with respect to its
+// height and slopes, for the adjoint: with C = a exp(i phi),
+// dC/dtheta = C (d ln a / dtheta + i d phi / dtheta).  The geometry is
+// recomputed from the facet fields exactly as the forward does.  Terms:
+//   ln a = 1/2 ln(|G0|^2 A / mss) + ln(1 + tan^2) - tan^2/(2 mss)
+//          - (2/gamma) sin^2 + 2 ln H - 2 ln R,   phi = -2 pi R k2 (mod 2 pi)
+//   tan^2 = |c|^2/q^2, c = d x m, q = d . m, m = (-sx, -sy, 1), d = S - P,
+//   dd/dh = (0, 0, -1), dm/dsx = (-1, 0, 0), dm/dsy = (0, -1, 0),
+//   ln A = ln jac + 1/2 ln(1 + sx^2 + sy^2), dR/dh = -d_z / R.
+struct FacetDeriv {
+  double lnh, phih;   // d ln a / dh, d phi / dh
+  double lnsx, lnsy;  // d ln a / dsx, d ln a / dsy (phi does not depend on slopes)
+};
+
+template <typename Real>
+__device__ __forceinline__ FacetDeriv facet_derivatives(const RadarP& rp, const GridP& gp, int ix,
+                                                        int iy, Real Dx, Real Dy, Real h, Real sx,
+                                                        Real sy) {
+  const double x0 = gp.x_origin + (double)ix * gp.dx;
+  const double y0 = gp.y_origin + (double)iy * gp.dy;
+  const double dx = rp.sat_x - (x0 + (double)Dx);
+  const double dy = rp.sat_y1 - (y0 + (double)Dy);
+  const double dz = rp.altitude - (double)h;
+  const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double sxd = (double)sx, syd = (double)sy;
+  const double mx = -sxd, my = -syd;
+  const double cx = dy - dz * my, cy = dz * mx - dx, cz = dx * my - dy * mx;
+  const double q = dx * mx + dy * my + dz;
+  const double c2 = cx * cx + cy * cy + cz * cz;
+  const double q2 = q * q;
+  const double tan2 = c2 / q2;
+  const double sin2 = (dx * dx + dy * dy) / (r * r);
+  const double s2 = 1.0 + sxd * sxd + syd * syd;
+  const double k_tan = 1.0 / (1.0 + tan2) - 0.5 * rp.inv_mss;   // d ln a / d tan^2
+  auto dtan = [&](double dcx, double dcy, double dcz, double dq) {
+    return 2.0 * (cx * dcx + cy * dcy + cz * dcz) / q2 - 2.0 * c2 * dq / (q2 * q);
+  };
+  FacetDeriv D;
+  const double dR = -dz / r;
+  D.lnh = k_tan * dtan(-syd, sxd, 0.0, -1.0) - rp.two_over_gamma * (-2.0 * sin2 * dR / r) -
+          2.0 * dR / r;
+  D.phih = -6.283185307179586476925 * rp.k2 * dR;
+  D.lnsx = 0.5 * sxd / s2 + k_tan * dtan(0.0, -dz, dy, -dx);
+  D.lnsy = 0.5 * syd / s2 + k_tan * dtan(dz, 0.0, -dx, -dy);
+  return D;
+}
+
+}  // namespace simk

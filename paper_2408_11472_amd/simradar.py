@@ -46,10 +46,16 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_get_precision", "sim_workspace_size", "sim_set_workspace",
             "sim_surface_update", "sim_range_doppler_accumulate",
             "sim_update_and_accumulate", "sim_segments_to_iq",
+            "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
+            "sim_range_doppler_accumulate_adjoint",
+            "sim_batch_create", "sim_batch_destroy", "sim_batch_workspace_size",
+            "sim_batch_run", "sim_set_tuning",
             "sim_profile_enable", "sim_profile_read")
 
+SIM_TUNE_ROW_BANDS = 0
+
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
-                "reduce_partials", "segments_to_iq")
+                "reduce_partials", "segments_to_iq", "adjoint", "clear")
 
 
 class sim_grid(ctypes.Structure):
@@ -76,7 +82,7 @@ class sim_facets(ctypes.Structure):
 
 
 class sim_kernel_times(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_uint64 * 6)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
 
 
 _P = ctypes.c_void_p
@@ -103,6 +109,23 @@ _sig = {
                                                  ctypes.POINTER(sim_radar), _D, _I, _P, _I,
                                                  _P, _P, _P]),
     "sim_segments_to_iq": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P]),
+    "sim_waveform_loss": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P, _P, _P]),
+    "sim_waveform_loss_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P,
+                                                 _P, _P, _P]),
+    "sim_segments_to_iq_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P,
+                                                  _P]),
+    "sim_range_doppler_accumulate_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid),
+                                                            ctypes.POINTER(sim_facets),
+                                                            ctypes.POINTER(sim_radar), _D, _I,
+                                                            _P, _I, _P, _P, _P, _P]),
+    "sim_batch_create": (ctypes.c_int, [_P, _I, ctypes.POINTER(sim_grid),
+                                        ctypes.POINTER(sim_radar), ctypes.POINTER(_I),
+                                        ctypes.POINTER(_P)]),
+    "sim_batch_destroy": (ctypes.c_int, [_P]),
+    "sim_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "sim_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                     ctypes.POINTER(_P), ctypes.c_int, _P]),
+    "sim_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "sim_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "sim_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(sim_kernel_times)]),
 }
@@ -180,6 +203,66 @@ def sim_update_and_accumulate(ctx, grid, spec0_ptr, radar, t, j, t_fast_ptr, n_s
 def sim_segments_to_iq(ctx, radar, t_fast_ptr, n_spec, y_ptr, stream) -> None:
     _check("sim_segments_to_iq",
            _lib.sim_segments_to_iq(ctx, ctypes.byref(radar), t_fast_ptr, n_spec, y_ptr, stream))
+
+
+def sim_waveform_loss(ctx, radar, y_ptr, n_pulses, target_ptr, p_ptr, loss_ptr, stream) -> None:
+    _check("sim_waveform_loss",
+           _lib.sim_waveform_loss(ctx, ctypes.byref(radar), y_ptr, n_pulses, target_ptr, p_ptr,
+                                  loss_ptr, stream))
+
+
+def sim_waveform_loss_adjoint(ctx, radar, y_ptr, n_pulses, p_ptr, target_ptr, scale_ptr,
+                              y_bar_ptr, stream) -> None:
+    _check("sim_waveform_loss_adjoint",
+           _lib.sim_waveform_loss_adjoint(ctx, ctypes.byref(radar), y_ptr, n_pulses, p_ptr,
+                                          target_ptr, scale_ptr, y_bar_ptr, stream))
+
+
+def sim_segments_to_iq_adjoint(ctx, radar, y_bar_ptr, n_spec, t_bar_ptr, stream) -> None:
+    _check("sim_segments_to_iq_adjoint",
+           _lib.sim_segments_to_iq_adjoint(ctx, ctypes.byref(radar), y_bar_ptr, n_spec, t_bar_ptr,
+                                           stream))
+
+
+def sim_range_doppler_accumulate_adjoint(ctx, grid, facets, radar, t, j, t_bar_ptr, n_spec,
+                                         gh_ptr, gsx_ptr, gsy_ptr, stream) -> None:
+    _check("sim_range_doppler_accumulate_adjoint",
+           _lib.sim_range_doppler_accumulate_adjoint(ctx, ctypes.byref(grid),
+                                                     ctypes.byref(facets), ctypes.byref(radar),
+                                                     t, j, t_bar_ptr, n_spec, gh_ptr, gsx_ptr,
+                                                     gsy_ptr, stream))
+
+
+def sim_set_tuning(ctx, key, value) -> None:
+    _check("sim_set_tuning", _lib.sim_set_tuning(ctx, key, value))
+
+
+def sim_batch_create(ctx, grids, radars, n_updates) -> int:
+    n = len(grids)
+    ga = (sim_grid * n)(*grids)
+    ra = (sim_radar * n)(*radars)
+    ua = (_I * n)(*n_updates)
+    b = _P()
+    _check("sim_batch_create", _lib.sim_batch_create(ctx, n, ga, ra, ua, ctypes.byref(b)))
+    return b.value
+
+
+def sim_batch_destroy(batch) -> None:
+    _check("sim_batch_destroy", _lib.sim_batch_destroy(batch))
+
+
+def sim_batch_workspace_size(batch) -> int:
+    n = ctypes.c_size_t()
+    _check("sim_batch_workspace_size", _lib.sim_batch_workspace_size(batch, ctypes.byref(n)))
+    return n.value
+
+
+def sim_batch_run(batch, spec_ptrs, t_ptrs, y_ptrs, use_graph, stream) -> None:
+    n = len(spec_ptrs)
+    sa = (_P * n)(*spec_ptrs)
+    ta = (_P * n)(*t_ptrs)
+    ya = None if y_ptrs is None else (_P * n)(*y_ptrs)
+    _check("sim_batch_run", _lib.sim_batch_run(batch, sa, ta, ya, 1 if use_graph else 0, stream))
 
 
 def sim_profile_enable(ctx, enable: bool) -> None:
@@ -327,6 +410,10 @@ class Simulator:
                            self._stream(stream))
         return y
 
+    def set_row_bands(self, n: int):
+        """Blocks of the fused row pass (a power of two <= 512; 0 = default)."""
+        sim_set_tuning(self.ctx, SIM_TUNE_ROW_BANDS, int(n))
+
     def profile(self, enable: bool = True):
         """Start (clearing) or stop per-kernel event timing."""
         sim_profile_enable(self.ctx, enable)
@@ -334,6 +421,61 @@ class Simulator:
     def profile_read(self) -> dict:
         """{kernel kind: (summed ms, launches)} since profiling was enabled."""
         return sim_profile_read(self.ctx)
+
+    # differentiable chain
+    def waveform_loss(self, y, target=None, stream=None):
+        """(P, loss) with P[g] = mean_x |y[x][g]|^2, loss = sum (P - target)^2
+        (loss is None when target is None)."""
+        r = self.radar
+        n_pulses = y.shape[0]
+        P = self.torch.empty(r.n_gates, dtype=self.real_dtype, device=self.device)
+        L = None
+        tptr = None
+        if target is not None:
+            L = self.torch.empty(1, dtype=self.real_dtype, device=self.device)
+            tptr = self._need(target, self.real_dtype, (r.n_gates,), "target")
+        sim_waveform_loss(self.ctx, self.radar,
+                          self._need(y, self.complex_dtype, (n_pulses, r.n_gates), "y"),
+                          n_pulses, tptr, P.data_ptr(), None if L is None else L.data_ptr(),
+                          self._stream(stream))
+        return P, (None if L is None else L[0])
+
+    def waveform_loss_adjoint(self, y, P, target, scale=None, stream=None):
+        r = self.radar
+        n_pulses = y.shape[0]
+        yb = self.torch.empty_like(y)
+        sim_waveform_loss_adjoint(
+            self.ctx, self.radar, self._need(y, self.complex_dtype, (n_pulses, r.n_gates), "y"),
+            n_pulses, self._need(P, self.real_dtype, (r.n_gates,), "P"),
+            self._need(target, self.real_dtype, (r.n_gates,), "target"),
+            None if scale is None else self._need(scale, self.real_dtype, (1,), "scale"),
+            yb.data_ptr(), self._stream(stream))
+        return yb
+
+    def segments_to_iq_adjoint(self, y_bar, n_spec, stream=None):
+        r = self.radar
+        tb = self.torch.empty((n_spec, r.n_gates, r.n_doppler), dtype=self.complex_dtype,
+                              device=self.device)
+        sim_segments_to_iq_adjoint(
+            self.ctx, self.radar,
+            self._need(y_bar, self.complex_dtype, ((n_spec - 1) * r.n_fast, r.n_gates), "y_bar"),
+            n_spec, tb.data_ptr(), self._stream(stream))
+        return tb
+
+    def range_doppler_accumulate_adjoint(self, facets, t, j, t_bar, out=None, stream=None):
+        g = self.grid
+        r = self.radar
+        n_spec = t_bar.shape[0]
+        if out is None:
+            out = [self.torch.empty((g.ny, g.nx), dtype=self.real_dtype, device=self.device)
+                   for _ in range(3)]
+        for o in out:
+            self._need(o, self.real_dtype, (g.ny, g.nx), "gradient")
+        sim_range_doppler_accumulate_adjoint(
+            self.ctx, self.grid, self._facets_struct(facets), self.radar, float(t), int(j),
+            self._need(t_bar, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_bar"),
+            n_spec, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), self._stream(stream))
+        return {"h": out[0], "sx": out[1], "sy": out[2]}
 
     def run(self, spec0, n_updates, t_fast=None, y=None, counters=None, stream=None):
         """Algorithm 1 and post-processing: U + 1 spectra, then Y."""
@@ -343,3 +485,60 @@ class Simulator:
             t = (j * r.n_fast) / r.prf_hz
             self.update_and_accumulate(spec0, t, j, t_fast, counters=counters, stream=stream)
         return t_fast, self.segments_to_iq(t_fast, y, stream=stream)
+
+
+class Batch:
+    """Independent realisations run together on one context (update-major on
+    one stream, optionally as one replayed HIP graph).  ``members`` is a list
+    of (grid, radar, n_updates)."""
+
+    def __init__(self, members, precision=SIM_PREC_FP32_PHASE64, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.precision = precision
+        self.complex_dtype = torch.complex128 if precision == SIM_PREC_FP64 else torch.complex64
+        self.grids = [grid_struct(g) for g, _, _ in members]
+        self.radars = [radar_struct(r) for _, r, _ in members]
+        self.updates = [int(u) for _, _, u in members]
+        self.ctx = sim_create(device, precision)
+        self.batch = sim_batch_create(self.ctx, self.grids, self.radars, self.updates)
+        nbytes = sim_batch_workspace_size(self.batch)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        sim_set_workspace(self.ctx, (self.workspace.data_ptr() + 255) & ~255, nbytes)
+        self.stream = torch.cuda.Stream(self.device)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            sim_batch_destroy(self.batch)
+            self.batch = None
+        if getattr(self, "ctx", None):
+            sim_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_outputs(self):
+        T = [self.torch.empty((u + 1, r.n_gates, r.n_doppler), dtype=self.complex_dtype,
+                              device=self.device) for r, u in zip(self.radars, self.updates)]
+        Y = [self.torch.empty((u * r.n_fast, r.n_gates), dtype=self.complex_dtype,
+                              device=self.device) for r, u in zip(self.radars, self.updates)]
+        return T, Y
+
+    def run(self, specs, T, Y=None, use_graph=False):
+        """Run the batch on the batch's own stream (ordered after the current
+        stream's work, and the current stream waits for it)."""
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        for x in list(specs) + list(T) + (list(Y) if Y is not None else []):
+            if not x.is_cuda or x.dtype != self.complex_dtype or not x.is_contiguous():
+                raise ValueError("batch buffers must be contiguous complex CUDA tensors")
+        sim_batch_run(self.batch, [x.data_ptr() for x in specs], [x.data_ptr() for x in T],
+                      None if Y is None else [x.data_ptr() for x in Y], use_graph,
+                      self.stream.cuda_stream)
+        cur.wait_stream(self.stream)
+        return T, Y

@@ -154,8 +154,10 @@ def test_accumulate_adds_and_repeats(prec, pcode, npdt):
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
 @pytest.mark.parametrize("nx,ny,cwm", [(16, 16, 1), (64, 32, 1), (32, 128, 0), (256, 256, 1),
-                                       (1024, 64, 1)])
+                                       (1024, 64, 1), (8192, 32, 1), (32, 16384, 1)])
 def test_surface_update_matches_oracle(prec, pcode, npdt, nx, ny, cwm):
+    if prec == "fp64" and ny > 8192:
+        pytest.skip("ny > 8192 is float-only (LDS of one column)")
     simradar = _sim()
     print_case("surface", prec, nx, ny, cwm)
     wl = workloads.tiny(nx=nx, ny=ny, spacing=1.5, cwm=cwm, seed=nx + ny)
@@ -200,12 +202,18 @@ def _count_edge_ok(code, code_ref, fac, wl, t, edge_tol):
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
-@pytest.mark.parametrize("which", ["tiny", "small_256"])
+@pytest.mark.parametrize("which", ["tiny", "small_256", "wide_8192"])
 def test_update_and_accumulate_end_to_end(prec, pcode, npdt, which):
     simradar = _sim()
     print_case("fused", prec, which)
-    wl = workloads.small_256() if which == "small_256" else workloads.tiny(
-        nx=64, ny=64, spacing=2.0, n_gates=32, n_doppler=16, n_fast=16, n_updates=3)
+    if which == "small_256":
+        wl = workloads.small_256()
+    elif which == "wide_8192":
+        wl = workloads.tiny(nx=8192, ny=64, spacing=1.0, n_gates=64, n_doppler=64, n_fast=64,
+                            n_updates=3)
+    else:
+        wl = workloads.tiny(nx=64, ny=64, spacing=2.0, n_gates=32, n_doppler=16, n_fast=16,
+                            n_updates=3)
     spec = _spec(wl)
     sim = simradar.Simulator(wl.grid, wl.radar, pcode)
     spec_t = torch.as_tensor(spec.astype(np.complex64 if npdt == np.float32 else np.complex128),
