@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--workload", default="track_4096")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 context")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default band count of the fused row pass")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="before timing, copy a buffer of this size once (a plain copy kernel "
                         "of known traffic, to scale the HBM byte counters of a profiler run)")
@@ -152,6 +154,10 @@ def main():
             continue
         sim = simradar.Simulator(g, wl.radar, prec)
         spec_t = torch.as_tensor(spec.astype(cdt), device="cuda")
+        tuning = None
+        if not a.no_autotune:
+            from paper_2408_11472_amd import autotune
+            tuning = autotune.tune(sim, spec_t, use_cache=False)
         dt, prof, T, Y = timed_steps(sim, spec_t, wl, a.steps, a.warmup, torch)
         ms_step = dt / a.steps * 1e3
         results[name] = {
@@ -161,6 +167,7 @@ def main():
             "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items() if v[1]},
             "roofline": roofline(prof, wl, scale, measured_ok),
             "finite": bool(torch.isfinite(torch.view_as_real(Y)).all().item()),
+            "tuning": tuning,
         }
         print(f"[bench] {name}: {ms_step:.2f} ms/step  "
               f"{results[name]['facet_updates_per_s']:.3e} facet-updates/s  "
@@ -191,6 +198,7 @@ def main():
         "iq_pulses_per_s": round(r32["iq_pulses_per_s"], 1),
         "kernels_ms_per_step": r32["kernels_ms_per_step"],
         "roofline": r32["roofline"],
+        "tuning": r32["tuning"],
     }
     if "fp64" in results:
         r64 = results["fp64"]

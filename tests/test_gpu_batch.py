@@ -82,3 +82,27 @@ def test_graph_replays_match_eager(prec, pcode, cdt):
         for a, b in zip(Y, Y_eager):
             assert rel_l2(a.cpu().numpy(), b) <= (1e-13 if prec == "fp64" else 1e-6), rep
     batch.close()
+
+
+@pytest.mark.parametrize("prec,pcode,cdt,tol", [("fp64", 0, np.complex128, 1e-13),
+                                                ("fp32", 1, np.complex64, 1e-6)])
+def test_band_count_changes_only_summation_order(prec, pcode, cdt, tol, tmp_path, monkeypatch):
+    from paper_2408_11472_amd import autotune, simradar
+    print_case("bands", prec)
+    monkeypatch.setenv("SIMRADAR_TUNING_CACHE", str(tmp_path / "tuning.json"))
+    wl = workloads.small_256()
+    spec = torch.as_tensor(_spec(wl).astype(cdt), device="cuda")
+    sim = simradar.Simulator(wl.grid, wl.radar, pcode)
+    outs = []
+    for nb in (0, 8, 32):
+        sim.set_row_bands(nb)
+        T = sim.empty_spectra(wl.n_spec)
+        sim.update_and_accumulate(spec, wl.update_time(4), 4, T)
+        torch.cuda.synchronize()
+        outs.append(T.cpu().numpy())
+    for o in outs[1:]:
+        assert rel_l2(o, outs[0]) <= tol
+    entry = autotune.tune(sim, spec, repeats=2)
+    assert entry["row_bands"] in autotune.CANDIDATE_BANDS
+    assert autotune.tune(sim, spec)["row_bands"] == entry["row_bands"]   # cached
+    sim.close()
