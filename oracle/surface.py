@@ -26,8 +26,9 @@ J = n_z and its slopes sx = -n_x/n_z, sy = -n_y/n_z.  The displacement of the
 facet over the pulse pair is P(t + dt) - P(t), both surfaces evaluated in full
 as Algorithm 1 does.
 
-Parity: pinned by a direct (non-FFT) modal sum on small grids, finite
-differences of that sum for every derivative field and for the facet normal,
+Parity: pinned by a direct (non-FFT) modal sum on small grids (the row-subset
+evaluation as well), finite differences of that sum for every derivative
+field and for the facet normal,
 the closed-form single-mode CWM (trochoid) profile and phase speed, and the
 exact variance identities of the half-plane spectrum.
 """
@@ -47,23 +48,30 @@ def wavenumbers(grid):
     return np.meshgrid(kx, ky)
 
 
-def multipliers(grid):
-    """Spectral multiplier M_F(k) of each field (dict of complex arrays)."""
+def multipliers(grid, names=FIELDS):
+    """Spectral multiplier M_F(k) of each named field (dict of complex arrays)."""
+    make = _multiplier_makers(grid)
+    return {n: make[n]() for n in names}
+
+
+def _multiplier_makers(grid):
+    """One callable per field that builds its multiplier on demand."""
     KX, KY = wavenumbers(grid)
     K = np.hypot(KX, KY)
     inv_k = np.zeros_like(K)
     np.divide(1.0, K, out=inv_k, where=K > 0)
     d = 1.0 if grid.cwm else 0.0
-    return {
-        "h": np.ones_like(K, dtype=complex),
-        "disp_x": d * 1j * KX * inv_k,
-        "disp_y": d * 1j * KY * inv_k,
-        "h_x": 1j * KX,
-        "h_y": 1j * KY,
-        "dx_x": d * (-(KX * KX) * inv_k) + 0j,
-        "dx_y": d * (-(KX * KY) * inv_k) + 0j,
-        "dy_y": d * (-(KY * KY) * inv_k) + 0j,
+    make = {
+        "h": lambda: np.ones_like(K, dtype=complex),
+        "disp_x": lambda: d * 1j * KX * inv_k,
+        "disp_y": lambda: d * 1j * KY * inv_k,
+        "h_x": lambda: 1j * KX,
+        "h_y": lambda: 1j * KY,
+        "dx_x": lambda: d * (-(KX * KX) * inv_k) + 0j,
+        "dx_y": lambda: d * (-(KX * KY) * inv_k) + 0j,
+        "dy_y": lambda: d * (-(KY * KY) * inv_k) + 0j,
     }
+    return make
 
 
 def evolved(spec0, grid, t):
@@ -87,9 +95,28 @@ def fields(spec0, grid, t, names=FIELDS):
     numpy's ifft2 carries a 1/(nx ny) factor and the + sign in the exponent,
     so the modal sum is ifft2(.) * nx * ny."""
     c = evolved(spec0, grid, t)
-    m = multipliers(grid)
+    m = multipliers(grid, names)
     scale = grid.nx * grid.ny
     return {n: np.real(np.fft.ifft2(m[n] * c)) * scale for n in names}
+
+
+def fields_rows(spec0, grid, t, rows, names=FIELDS):
+    """The same fields evaluated only on the grid rows ``rows`` (shape
+    (len(rows), nx) each), for sampling grids too large to transform whole.
+
+    The modal sum is taken along y by its definition, a sum over ky of
+    M_F c exp(i ky y0) with the exponent reduced exactly as
+    2 pi ((n_y iy) mod ny) / ny, and then along x by numpy's inverse FFT."""
+    rows = np.asarray(rows, dtype=np.int64)
+    c = evolved(spec0, grid, t)
+    n_y = np.fft.fftfreq(grid.ny, d=1.0 / grid.ny).round().astype(np.int64)
+    e = np.exp(2j * np.pi * (np.outer(rows, n_y) % grid.ny) / grid.ny)    # (r, ny)
+    make = _multiplier_makers(grid)
+    out = {}
+    for n in names:
+        part = e @ (make[n]() * c)                                          # (r, nx)
+        out[n] = np.real(np.fft.ifft(part, axis=1)) * grid.nx
+    return out
 
 
 def facet_normal(f):
@@ -113,6 +140,17 @@ def facets(spec0, grid, t, dt):
     """
     f0 = fields(spec0, grid, t)
     f1 = fields(spec0, grid, t + dt, names=("h", "disp_x", "disp_y"))
+    return _facets_from_fields(f0, f1)
+
+
+def facets_rows(spec0, grid, t, dt, rows):
+    """``facets`` restricted to the grid rows ``rows`` (shape (len(rows), nx))."""
+    f0 = fields_rows(spec0, grid, t, rows)
+    f1 = fields_rows(spec0, grid, t + dt, rows, names=("h", "disp_x", "disp_y"))
+    return _facets_from_fields(f0, f1)
+
+
+def _facets_from_fields(f0, f1):
     nx, ny, nz = facet_normal(f0)
     with np.errstate(divide="ignore", invalid="ignore"):
         sx = -nx / nz

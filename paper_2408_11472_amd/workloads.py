@@ -15,6 +15,7 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
 import math
+import random
 
 WIN_SQRT_TRIANGLE = 0        # weights of eq. (1)
 WIN_SQRT_RAISED_COSINE = 1   # power-complementary raised-cosine cross-fade
@@ -151,6 +152,23 @@ def stress_8192x16384() -> Workload:
                 128, 512, 128, 512)
 
 
+def batched_16() -> list:
+    """Sixteen independent realisations of uneven size run as one batch:
+    6 x 1024^2, 5 x 2048^2, 3 x 4096^2 and 2 x 8192^2 facets at 1 m (2.1e8 in
+    all), seeds 100..115 with the SWH of each drawn uniformly in [1, 6] m from
+    its seed (peak wavelength 50 SWH), 128 gates x 256 bins, n_fast 256,
+    32 updates -> 33 spectra and 8192 pulses each."""
+    sides = [1024] * 6 + [2048] * 5 + [4096] * 3 + [8192] * 2
+    out = []
+    for r, n in enumerate(sides):
+        seed = 100 + r
+        swh = random.Random(seed).uniform(1.0, 6.0)
+        out.append(make(f"batch{r:02d}_{n}sq_1m_g128_n256_u32", n, n, 1.0,
+                        Sea(swh=swh, peak_wavelength=50.0 * swh, seed=seed),
+                        128, 256, 256, 32))
+    return out
+
+
 def tiny(nx=16, ny=16, spacing=2.0, n_gates=16, n_doppler=8, n_fast=8,
          n_updates=2, seed=11, swh=2.0, window=WIN_SQRT_TRIANGLE, cwm=1,
          **radar_kw) -> Workload:
@@ -167,4 +185,8 @@ ALL = {
     "track_4096": track_4096,
     "gradient_2048": gradient_2048,
     "stress_8192x16384": stress_8192x16384,
+}
+
+BATCHES = {
+    "batched_16": batched_16,
 }

@@ -34,6 +34,32 @@ def test_fields_match_direct_modal_sum(nx, ny, cwm):
     np.testing.assert_allclose(f["disp_y"], Dy, atol=1e-12 * scale, rtol=0)
 
 
+@pytest.mark.parametrize("nx,ny,rows", [(16, 32, [0, 5, 31]), (32, 16, [15, 2]), (8, 64, [63])])
+def test_row_subset_fields_match_direct_modal_sum(nx, ny, rows):
+    wl, spec = _tiny(nx, ny, 1, seed=nx + ny)
+    g = wl.grid
+    t = 1.91
+    f = osurf.fields_rows(spec, g, t, rows)
+    modes = brute.mode_list(spec, nx, ny, g.dx, g.dy)
+    X, Y = np.meshgrid(np.arange(nx) * g.dx, np.asarray(rows) * g.dy)
+    h, Dx, Dy = brute.surface_at(modes, X, Y, t)
+    scale = np.max(np.abs(h))
+    np.testing.assert_allclose(f["h"], h, atol=1e-12 * scale, rtol=0)
+    np.testing.assert_allclose(f["disp_x"], Dx, atol=1e-12 * scale, rtol=0)
+    np.testing.assert_allclose(f["disp_y"], Dy, atol=1e-12 * scale, rtol=0)
+    # derivative fields and facets: the rows of the whole-grid evaluation
+    # (whose derivatives are pinned by finite differences below)
+    full = osurf.fields(spec, g, t)
+    for k in osurf.FIELDS:
+        s = max(1e-300, np.max(np.abs(full[k])))
+        np.testing.assert_allclose(f[k], full[k][rows], atol=1e-12 * s, rtol=0)
+    fr = osurf.facets_rows(spec, g, t, 1e-3, rows)
+    ff = osurf.facets(spec, g, t, 1e-3)
+    for k in osurf.FACET_FIELDS:
+        s = max(1e-300, np.max(np.abs(ff[k])))
+        np.testing.assert_allclose(fr[k], ff[k][rows], atol=1e-11 * s, rtol=0)
+
+
 @pytest.mark.parametrize("cwm", [0, 1])
 def test_derivative_fields_match_finite_differences(cwm):
     nx = ny = 16
