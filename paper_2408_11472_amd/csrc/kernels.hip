@@ -86,17 +86,27 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       if (group == 0) {
         z = cadd(p, q);
       } else {
-        // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt)
+        // e^{-i w dt} - 1 = -2 sin^2(w dt / 2) - i sin(w dt).  Over one pulse
+        // interval w dt stays far below 0.01 rad and the sines are taken
+        // from their Taylor series (to the a^7 term, below float and double
+        // rounding there); larger steps use sin(w dt) = 2 sin(w dt / 2)
+        // cos(w dt / 2) with one sincospi of the half angle, reduced in
+        // double by whole turns of 2 (w dt / 4 pi).
         const Real a = (Real)(w * dt);
         Real sh, sf;
         if (a < (Real)0.01) {
           const Real a2 = a * a;
           sh = (Real)0.5 * a *
-               ((Real)1 - a2 / (Real)24 * ((Real)1 - a2 / (Real)80 * ((Real)1 - a2 / (Real)168)));
-          sf = a * ((Real)1 - a2 / (Real)6 * ((Real)1 - a2 / (Real)20 * ((Real)1 - a2 / (Real)42)));
+               ((Real)1 - a2 * (Real)(1.0 / 24) *
+                              ((Real)1 - a2 * (Real)(1.0 / 80) * ((Real)1 - a2 * (Real)(1.0 / 168))));
+          sf = a * ((Real)1 - a2 * (Real)(1.0 / 6) *
+                                  ((Real)1 - a2 * (Real)(1.0 / 20) * ((Real)1 - a2 * (Real)(1.0 / 42))));
         } else {
-          sh = sin((Real)0.5 * a);
-          sf = sin(a);
+          double qrev = w * dt * (0.5 / twopi);
+          qrev -= __builtin_rint(qrev);
+          Real ch;
+          sincos_pi((Real)(2.0 * qrev), &sh, &ch);
+          sf = (Real)2 * sh * ch;
         }
         const cplx<Real> al = mk<Real>((Real)-2 * sh * sh, -sf);
         z = cadd(cmul(p, al), cmul(q, cconj(al)));
@@ -205,9 +215,10 @@ __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes
     const Real nxn = dxy * hy[m] - hx[m] * ((Real)1 + dyy);
     const Real nyn = hx[m] * dxy - ((Real)1 + dxx[m]) * hy[m];
     const Real nzn = ((Real)1 + dxx[m]) * ((Real)1 + dyy) - dxy * dxy;
+    const Real inz = approx_rcp(nzn);
     F.jac[m] = nzn;
-    F.sx[m] = -nxn / nzn;
-    F.sy[m] = -nyn / nzn;
+    F.sx[m] = -nxn * inz;
+    F.sy[m] = -nyn * inz;
   }
 }
 

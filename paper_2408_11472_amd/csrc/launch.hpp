@@ -22,11 +22,13 @@ constexpr int kMaxLog2Row = 13;             // .. 8192 along x
 
 __host__ __device__ constexpr size_t lpad_c(size_t i) { return i + (i >> 4); }
 
-// Column pass: CPB adjacent columns per block, ny/16 threads per column.
+// Column pass: CPB adjacent columns per block, ny/16 threads per column,
+// as many columns as fit kColLds of LDS (one column at least).
+constexpr size_t kColLds = kLdsBudget;
 __host__ __device__ constexpr int col_cpb(int log2ny, int cs) {
   int cpb = 16;
   while (cpb > 1 && ((long)cpb * ((1 << log2ny) / 16) > 1024 ||
-                     (size_t)cpb * lpad_c((size_t)1 << log2ny) * cs > kLdsBudget))
+                     (size_t)cpb * lpad_c((size_t)1 << log2ny) * cs > kColLds))
     cpb >>= 1;
   return cpb;
 }

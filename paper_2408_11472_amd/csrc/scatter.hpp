@@ -65,17 +65,18 @@ __device__ __forceinline__ int scatterer(const RadarP& rp, const GridP& gp, int 
   const Real cy = (Real)(ddz * msx - ddx);
   const Real cz = (Real)(ddx * msy - ddy * msx);
   const Real qr = (Real)q;
-  const Real tan2 = (cx * cx + cy * cy + cz * cz) / (qr * qr);
+  const Real iq = approx_rcp(qr);
+  const Real tan2 = (cx * cx + cy * cy + cz * cz) * (iq * iq);
   const Real sec2 = (Real)1 + tan2;
-  const Real rr = (Real)r;
+  const Real ir = approx_rcp((Real)r);
   const Real fx = (Real)ddx, fy = (Real)ddy;
-  const Real sin2 = (fx * fx + fy * fy) / (rr * rr);
-  const Real hr = (Real)rp.altitude / rr;
+  const Real sin2 = (fx * fx + fy * fy) * (ir * ir);
+  const Real hr = (Real)rp.altitude * ir;
   // a = sqrt(sigma0 A) Ga (H/R)^2 with sigma0 = (|G0|^2/mss) sec^4 exp(-tan^2/mss)
   // and Ga = exp(-(2/gamma) sin^2): one exponential for both
-  const Real area = jac * sqrt((Real)1 + sx * sx + sy * sy) * (Real)rp.cell_area;
+  const Real area = jac * approx_sqrt((Real)1 + sx * sx + sy * sy) * (Real)rp.cell_area;
   const Real ex = -(Real)0.5 * (Real)rp.inv_mss * tan2 - (Real)rp.two_over_gamma * sin2;
-  const Real a = sqrt((Real)rp.fresnel_over_mss * area) * sec2 * exp(ex) * hr * hr;
+  const Real a = approx_sqrt((Real)rp.fresnel_over_mss * area) * sec2 * exp(ex) * hr * hr;
   Real sn, cs;
   sincos_pi((Real)2 * (Real)frac, &sn, &cs);
   C = mk<Real>(a * cs, -a * sn);

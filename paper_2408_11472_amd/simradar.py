@@ -522,6 +522,14 @@ class Batch:
         except Exception:
             pass
 
+    def profile(self, enable: bool = True):
+        """Start (clearing) or stop per-kernel event timing of eager runs."""
+        sim_profile_enable(self.ctx, enable)
+
+    def profile_read(self) -> dict:
+        """{kernel kind: (summed ms, launches)} since profiling was enabled."""
+        return sim_profile_read(self.ctx)
+
     def empty_outputs(self):
         T = [self.torch.empty((u + 1, r.n_gates, r.n_doppler), dtype=self.complex_dtype,
                               device=self.device) for r, u in zip(self.radars, self.updates)]

@@ -161,6 +161,11 @@ def test_surface_update_matches_oracle(prec, pcode, npdt, nx, ny, cwm):
     simradar = _sim()
     print_case("surface", prec, nx, ny, cwm)
     wl = workloads.tiny(nx=nx, ny=ny, spacing=1.5, cwm=cwm, seed=nx + ny)
+    # a sea of moderate steepness (SWH / peak wavelength <= 1/60): at the
+    # default 2 m on the 12 m peak of the narrow grids the CWM surface is
+    # near folding everywhere and the slopes are ill-conditioned in any
+    # float evaluation
+    wl.sea.swh = min(wl.sea.swh, wl.sea.peak_wavelength / 60.0)
     spec = _spec(wl)
     t, dt = 0.731, 1.0 / 18000.0
     ref = osurf.facets(spec, wl.grid, t, dt)
@@ -179,6 +184,29 @@ def test_surface_update_matches_oracle(prec, pcode, npdt, nx, ny, cwm):
             scale = np.sqrt(np.mean(ref["h"] ** 2)) if k in ("disp_x", "disp_y") else \
                 np.sqrt(np.mean(ref["dh"] ** 2))
         err = np.sqrt(np.mean((got - ref[k]) ** 2)) / scale
+        assert err <= tol, (k, err)
+
+
+@pytest.mark.parametrize("prec,pcode,npdt", PRECS)
+def test_surface_update_long_pair_interval(prec, pcode, npdt):
+    """A pair interval long enough that w dt leaves the small-angle range of
+    the increment multiplier (the other branch of the same formula)."""
+    simradar = _sim()
+    print_case("surface long dt", prec)
+    wl = workloads.tiny(nx=64, ny=64, spacing=1.0, seed=5)
+    wl.sea.swh = min(wl.sea.swh, wl.sea.peak_wavelength / 60.0)
+    spec = _spec(wl)
+    t, dt = 3.25, 0.2
+    ref = osurf.facets(spec, wl.grid, t, dt)
+    sim = simradar.Simulator(wl.grid, wl.radar, pcode)
+    spec_t = torch.as_tensor(spec.astype(np.complex64 if npdt == np.float32 else np.complex128),
+                             device="cuda")
+    out = sim.surface_update(spec_t, t, dt)
+    torch.cuda.synchronize()
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    for k in ("ddisp_x", "ddisp_y", "dh"):
+        got = out[k].cpu().numpy().astype(np.float64)
+        err = np.sqrt(np.mean((got - ref[k]) ** 2)) / np.sqrt(np.mean(ref[k] ** 2))
         assert err <= tol, (k, err)
 
 
