@@ -303,7 +303,10 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   int n_bands, band_rows;
   if (g->ny >= rpl.rpb) {
     n_bands = g->ny / rpl.rpb < target ? g->ny / rpl.rpb : target;
-    band_rows = g->ny / n_bands;
+    // rows per band: a whole number of row steps covering the grid
+    band_rows = (g->ny + n_bands - 1) / n_bands;
+    band_rows = (band_rows + rpl.rpb - 1) / rpl.rpb * rpl.rpb;
+    n_bands = (g->ny + band_rows - 1) / band_rows;
   } else {
     n_bands = 1;
     band_rows = rpl.rpb;

@@ -306,6 +306,7 @@ __device__ __forceinline__ int block_max(int a, int* scratch) {
 struct GridP {
   int nx, ny, log2nx, log2ny;
   int cwm;
+  int tlw, tlh;   // log2 of the plane tile width and height (set at launch)
   double dx, dy, x_origin, y_origin, gravity, sqrt_g;
 };
 

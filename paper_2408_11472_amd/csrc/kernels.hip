@@ -146,9 +146,25 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       v[m] = cmul(st[m], mul);
     }
     fft_seq<Real, LOG2NY, E, CPB, +1>(v, lds + (ixv - strip * CPB), sv, tw);
-    cplx<Real>* out = planes + (size_t)f * nx * ny + ixv;
+    // tiled plane layout (TW = CPB columns by TH rows per tile)
+    constexpr int LW = tile_lw(LOG2NY, sizeof(cplx<Real>));
+    constexpr int LH = tile_lh(LOG2NY, sizeof(cplx<Real>));
+    cplx<Real>* out = planes + (size_t)f * nx * ny;
+    const int cw = ixv & ((1 << LW) - 1), tx = ixv >> LW;
+    if constexpr (TPS % (1 << LH) == 0) {
+      // rows s + m TPS: the tile row advances by TPS / TH per slot
+      out += (((size_t)(sv >> LH) * (size_t)(nx >> LW) + tx) << (LW + LH)) +
+             ((sv & ((1 << LH) - 1)) << LW) + cw;
 #pragma unroll
-    for (int m = 0; m < E; ++m) out[(size_t)(sv + m * TPS) * nx] = v[m];
+      for (int m = 0; m < E; ++m) out[(size_t)m * TPS * nx] = v[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int iy = sv + m * TPS;
+        out[(((size_t)(iy >> LH) * (size_t)(nx >> LW) + tx) << (LW + LH)) +
+            ((iy & ((1 << LH) - 1)) << LW) + cw] = v[m];
+      }
+    }
   }
 }
 
@@ -158,13 +174,27 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
 
 constexpr int ER = kRowE;
 
+// Elements tr + m TPR of row iy of a plane in the tiled layout (tiles of
+// 2^lw columns by 2^lh rows).
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, int iy, bool valid,
-                                         int tr, cplx<Real>* v) {
+                                         int tr, int lw, int lh, cplx<Real>* v) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER;
-  const cplx<Real>* row = plane + (size_t)iy * nx + tr;
+  const size_t rb = ((size_t)(iy >> lh) << (LOG2NX + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  if ((TPR & ((1 << lw) - 1)) == 0) {
+    // columns tr + m TPR: TPR / TW tiles further per slot
+    const cplx<Real>* p =
+        plane + rb + ((size_t)(tr >> lw) << (lw + lh)) + (tr & ((1 << lw) - 1));
 #pragma unroll
-  for (int m = 0; m < ER; ++m) v[m] = valid ? row[m * TPR] : mk<Real>(0, 0);
+    for (int m = 0; m < ER; ++m) v[m] = valid ? p[(size_t)m * TPR << lh] : mk<Real>(0, 0);
+  } else {
+#pragma unroll
+    for (int m = 0; m < ER; ++m) {
+      const int ix = tr + m * TPR;
+      v[m] = valid ? plane[rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1))]
+                   : mk<Real>(0, 0);
+    }
+  }
 }
 
 // Inverse transform along x of one plane for one row.  The thread
@@ -172,11 +202,12 @@ __device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, i
 // recomputed per transform instead of being kept live across all six.
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ plane, int iy,
-                                              bool valid, int tr, cplx<Real>* lrow,
+                                              bool valid, int tr, const GridP& gp,
+                                              cplx<Real>* lrow,
                                               const cplx<Real>* __restrict__ tw, cplx<Real>* v) {
   int trv = tr;
   asm volatile("" : "+v"(trv));
-  load_row<Real, LOG2NX>(plane, iy, valid, trv, v);
+  load_row<Real, LOG2NX>(plane, iy, valid, trv, gp.tlw, gp.tlh, v);
   fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
 }
 
@@ -190,24 +221,25 @@ struct RowFacets {
 
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes, size_t psz,
-                                           int iy, bool valid, int tr, cplx<Real>* lrow,
+                                           int iy, bool valid, int tr, const GridP& gp,
+                                           cplx<Real>* lrow,
                                            const cplx<Real>* __restrict__ tw,
                                            RowFacets<Real>& F) {
   cplx<Real> v[ER];
   Real hx[ER], hy[ER], dxx[ER];
-  row_transform<Real, LOG2NX>(planes + 1 * psz, iy, valid, tr, lrow, tw, v);  // Dy + i h_x
+  row_transform<Real, LOG2NX>(planes + 1 * psz, iy, valid, tr, gp, lrow, tw, v);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 2 * psz, iy, valid, tr, lrow, tw, v);  // h_y + i Dx_x
+  row_transform<Real, LOG2NX>(planes + 2 * psz, iy, valid, tr, gp, lrow, tw, v);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     hy[m] = v[m].x;
     dxx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 3 * psz, iy, valid, tr, lrow, tw, v);  // Dx_y + i Dy_y
+  row_transform<Real, LOG2NX>(planes + 3 * psz, iy, valid, tr, gp, lrow, tw, v);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     const Real dxy = v[m].x, dyy = v[m].y;
@@ -224,23 +256,24 @@ __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes
 
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
-                                           int iy, bool valid, int tr, cplx<Real>* lrow,
+                                           int iy, bool valid, int tr, const GridP& gp,
+                                           cplx<Real>* lrow,
                                            const cplx<Real>* __restrict__ tw,
                                            RowFacets<Real>& F) {
   cplx<Real> v[ER];
-  row_transform<Real, LOG2NX>(planes + 0 * psz, iy, valid, tr, lrow, tw, v);  // h + i Dx
+  row_transform<Real, LOG2NX>(planes + 0 * psz, iy, valid, tr, gp, lrow, tw, v);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 4 * psz, iy, valid, tr, lrow, tw, v);  // dh + i dDx
+  row_transform<Real, LOG2NX>(planes + 4 * psz, iy, valid, tr, gp, lrow, tw, v);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.dh[m] = v[m].x;
     F.dDx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 5 * psz, iy, valid, tr, lrow, tw, v);  // dDy
+  row_transform<Real, LOG2NX>(planes + 5 * psz, iy, valid, tr, gp, lrow, tw, v);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
 }
@@ -257,11 +290,17 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
   const size_t psz = (size_t)nx * ny;
-  for (int iy0 = blockIdx.x * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
+  // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
+  // contiguous run of row chunks, so that the chunks sharing a plane tile
+  // (and its cache lines) are read through the same L2 at about the same time.
+  const int nblk = gridDim.x;
+  const int q = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                : blockIdx.x;
+  for (int iy0 = q * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
+    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -272,7 +311,7 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
         out.p[5][o] = F.jac[m];
       }
     }
-    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
+    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -321,14 +360,36 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   uint32_t cnt[5] = {0, 0, 0, 0, 0};
   uint32_t overflow = 0;
   const size_t psz = (size_t)nx * ny;
-  const int row_begin = band * wp.band_rows;
-  const int row_end = min(ny, row_begin + wp.band_rows);
-  for (int iy0 = row_begin; iy0 < row_begin + wp.band_rows; iy0 += RPB) {
+  // Row walk of this band.  The rows of one plane tile (TH rows) are split
+  // over M = TH / RPB bands that run on the same XCD (workgroups are dealt
+  // to the XCDs round robin) and walk the same tile rows together, so each
+  // cache line fetched for a tile is read by all of them through one L2.
+  // Group g of M bands takes tile rows [g band_rows, (g + 1) band_rows);
+  // member r takes rows r RPB .. r RPB + RPB - 1 of each.  Without enough
+  // bands for that, a band takes band_rows consecutive rows.
+  const int TH = 1 << gp.tlh;
+  const int M = TH > RPB ? TH / RPB : 1;
+  const int nb = wp.n_bands;
+  int first_tile_row = 0, member = 0, step_rows = RPB;
+  const bool grouped =
+      M > 1 && nb % (8 * M) == 0 && wp.band_rows % RPB == 0 && wp.band_rows * nb == ny;
+  const int n_steps = grouped ? wp.band_rows / RPB : (wp.band_rows + RPB - 1) / RPB;
+  if (grouped) {
+    const int l = band >> 3, per_xcd = nb >> 3;
+    const int group = (band & 7) * (per_xcd / M) + l / M;
+    member = l % M;
+    first_tile_row = group * n_steps;
+    step_rows = TH;
+  }
+  const int row_begin = grouped ? first_tile_row * TH + member * RPB : band * wp.band_rows;
+  const int row_end = grouped ? ny : min(ny, row_begin + wp.band_rows);
+  for (int k = 0; k < n_steps; ++k) {
+    const int iy0 = row_begin + k * step_rows;
     const int iy = iy0 + rl;
     const bool valid = iy < row_end;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
-    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, lrow, tw, F);
+    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
+    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
     int key[ER];
     cplx<Real> cv[ER];
     // opaque row coordinates: the grid positions of the facets are
@@ -735,6 +796,15 @@ accumulate_adjoint_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp,
 #define SIMK_COL_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 #define SIMK_ROW_SIZES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
 
+// The grid parameters with the plane tile geometry of this precision.
+template <typename Real>
+static GridP with_tiles(const GridP& gp) {
+  GridP g = gp;
+  g.tlw = tile_lw(gp.log2ny, sizeof(cplx<Real>));
+  g.tlh = tile_lh(gp.log2ny, sizeof(cplx<Real>));
+  return g;
+}
+
 template <typename Real, int L>
 static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, double t, double dt,
                             const void* tw, hipStream_t st) {
@@ -744,8 +814,8 @@ static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, dou
   } else {
     const int strips = gp.nx / col_cpb(L, cs);
     hipLaunchKernelGGL((colpass_kernel<Real, L>), dim3(2 * strips), dim3(col_threads(L, cs)),
-                       col_lds(L, cs), st, (const cplx<Real>*)spec, (cplx<Real>*)planes, gp, t, dt,
-                       (const cplx<Real>*)tw);
+                       col_lds(L, cs), st, (const cplx<Real>*)spec, (cplx<Real>*)planes,
+                       with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
     return hipGetLastError();
   }
 }
@@ -767,8 +837,8 @@ static hipError_t rowpass_facets_t(const void* planes, const GridP& gp, const Fa
                                    const void* tw, hipStream_t st) {
   const int blocks = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
   hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks), dim3(row_threads(L)),
-                     row_fft_lds(L, sizeof(cplx<Real>)), st, (const cplx<Real>*)planes, gp, fp,
-                     (const cplx<Real>*)tw);
+                     row_fft_lds(L, sizeof(cplx<Real>)), st, (const cplx<Real>*)planes,
+                     with_tiles<Real>(gp), fp, (const cplx<Real>*)tw);
   return hipGetLastError();
 }
 
@@ -791,8 +861,8 @@ static hipError_t rowpass_accumulate_t(const void* planes, const GridP& gp, cons
                                        const WinP& wp, void* Tj, int32_t* code, size_t lds,
                                        const void* tw, hipStream_t st) {
   hipLaunchKernelGGL((rowpass_accumulate_kernel<Real, L>), dim3(wp.n_bands), dim3(row_threads(L)),
-                     lds, st, (const cplx<Real>*)planes, gp, rp, wp, (cplx<Real>*)Tj, code,
-                     (const cplx<Real>*)tw);
+                     lds, st, (const cplx<Real>*)planes, with_tiles<Real>(gp), rp, wp,
+                     (cplx<Real>*)Tj, code, (const cplx<Real>*)tw);
   return hipGetLastError();
 }
 

@@ -39,6 +39,25 @@ __host__ __device__ constexpr size_t col_lds(int log2ny, int cs) {
   return (size_t)col_cpb(log2ny, cs) * lpad_c((size_t)1 << log2ny) * cs;
 }
 
+// Layout of the intermediate planes written by the column pass and read by
+// the row passes: tiles of TW = CPB columns by TH rows holding kTileElems
+// elements (64 bytes in float, 128 in double), tiles in row-major order.  A
+// column block then stores whole 64-byte segments instead of CPB-element
+// pieces of rows, and a row reads TW contiguous elements per tile; the TH
+// rows of a tile row are walked together by bands on one XCD.
+constexpr int kTileElems = 8;
+__host__ __device__ constexpr int ilog2_c(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+__host__ __device__ constexpr int tile_lw(int log2ny, int cs) {
+  return ilog2_c(col_cpb(log2ny, cs));
+}
+__host__ __device__ constexpr int tile_lh(int log2ny, int cs) {
+  return kTileElems / col_cpb(log2ny, cs) > 1 ? ilog2_c(kTileElems / col_cpb(log2ny, cs)) : 0;
+}
+
 // Row passes: ER values per thread, RPB rows per block.
 constexpr int kRowE = 8;
 __host__ __device__ constexpr int row_tpr(int log2nx) { return (1 << log2nx) / kRowE; }

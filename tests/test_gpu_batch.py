@@ -84,8 +84,10 @@ def test_graph_replays_match_eager(prec, pcode, cdt):
     batch.close()
 
 
+# Band counts regroup the window partial sums: a summation-order change over
+# cells of up to ~1e3 nearly coherent terms (eps * n_cell relative).
 @pytest.mark.parametrize("prec,pcode,cdt,tol", [("fp64", 0, np.complex128, 1e-13),
-                                                ("fp32", 1, np.complex64, 1e-6)])
+                                                ("fp32", 1, np.complex64, 1e-5)])
 def test_band_count_changes_only_summation_order(prec, pcode, cdt, tol, tmp_path, monkeypatch):
     from paper_2408_11472_amd import autotune, simradar
     print_case("bands", prec)
@@ -94,11 +96,15 @@ def test_band_count_changes_only_summation_order(prec, pcode, cdt, tol, tmp_path
     spec = torch.as_tensor(_spec(wl).astype(cdt), device="cuda")
     sim = simradar.Simulator(wl.grid, wl.radar, pcode)
     outs = []
-    for nb in (0, 8, 32):
+    with pytest.raises(simradar.SimError):
+        sim.set_row_bands(3)                     # band counts are powers of two
+    for nb in (0, 8, 32, 2, 64):
         sim.set_row_bands(nb)
         T = sim.empty_spectra(wl.n_spec)
-        sim.update_and_accumulate(spec, wl.update_time(4), 4, T)
+        cnt = sim.counters()
+        sim.update_and_accumulate(spec, wl.update_time(4), 4, T, counters=cnt)
         torch.cuda.synchronize()
+        assert int(cnt.cpu()[:5].sum()) == wl.n_facets, nb     # every row walked once
         outs.append(T.cpu().numpy())
     for o in outs[1:]:
         assert rel_l2(o, outs[0]) <= tol
