@@ -27,8 +27,11 @@ METRIC = "facet-updates/s + simulated IQ pulses/s (FP32+FP64-phase vs FP64, same
 # Algorithmic HBM bytes per facet and launch of each kernel (FP32 context;
 # FP64 doubles them): the column pass reads the spectrum once (8 B) and writes
 # six packed complex planes (48 B); the fused row pass reads the six planes
-# back (48 B) and writes nothing per facet.
-ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48}
+# back (48 B) and writes nothing per facet; on the split row path the facet
+# row pass reads the planes and writes nine facet fields (36 B), which the
+# facet accumulate reads back.
+ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48,
+                       "surface_rowpass": 48 + 36, "accumulate_facets": 36}
 
 # Counter measurements of the FP32 kernels on this workload (profiles/), valid
 # only for the kernel sources they were taken on: HBM bytes per launch from
@@ -92,7 +95,7 @@ def timed_steps(sim, spec_t, wl, steps, warmup, torch):
 
 def roofline(prof, wl, bytes_scale, measured_ok):
     """Dominant kernel against the HBM peak, from its event-timed launches."""
-    best = max((k for k in ALG_BYTES_PER_FACET), key=lambda k: prof[k][0])
+    best = max((k for k in ALG_BYTES_PER_FACET if prof[k][1]), key=lambda k: prof[k][0])
     ms, n = prof[best]
     avg_s = ms / 1e3 / n
     alg = ALG_BYTES_PER_FACET[best] * bytes_scale * wl.n_facets
@@ -101,7 +104,7 @@ def roofline(prof, wl, bytes_scale, measured_ok):
            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
            "alg_bytes_per_launch": alg}
-    if measured_ok and bytes_scale == 1:
+    if measured_ok and bytes_scale == 1 and best in MEASURED["traffic_bytes"]:
         out["traffic"] = MEASURED["traffic_bytes"][best]
         valu = MEASURED["valu_wave_instr"][best]
         out["valu_issue"] = {"achieved": round(valu / avg_s / 1e9, 1),

@@ -195,7 +195,10 @@ sim_status sim_range_doppler_accumulate(sim_ctx *ctx, const sim_grid *grid,
                                         int32_t *facet_code, void *stream);
 
 /* sim_surface_update followed by sim_range_doppler_accumulate for the pulse
- * pair (t, t + 1/PRF), fused: the facet set is never written to memory. */
+ * pair (t, t + 1/PRF).  On the fused row path (SIM_TUNE_ROW_PATH) the facet
+ * set is never written to memory; on the split path it goes through the
+ * workspace.  Either way the result is that of the two calls (up to the
+ * summation order of the partial spectra). */
 sim_status sim_update_and_accumulate(sim_ctx *ctx, const sim_grid *grid,
                                      const void *spec0, const sim_radar *radar,
                                      double t, int32_t j, void *t_fast,
@@ -285,6 +288,10 @@ sim_status sim_batch_run(sim_batch *batch, void *const *spec0, void *const *t_fa
  * Launch parameters that do not change results beyond summation order;
  * bench/autotune code sets them per context. */
 #define SIM_TUNE_ROW_BANDS 0      /* blocks of the fused row pass (bands of rows), 0 = default */
+#define SIM_TUNE_ROW_PATH 1       /* row path of sim_update_and_accumulate, one of:             */
+#define SIM_ROW_PATH_AUTO 0       /*   fused row pass where it runs without register spills   */
+#define SIM_ROW_PATH_FUSED 1      /*   fused row pass: facets stay on chip                    */
+#define SIM_ROW_PATH_SPLIT 2      /*   facet row pass into the workspace, then facet accumulate */
 sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 
 /* ---- per-kernel timing (profiling aid) ----------------------------------

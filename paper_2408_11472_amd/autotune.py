@@ -2,9 +2,10 @@
 summation order.
 
 For one (grid, radar, precision) it times the fused update+accumulate call
-with each candidate band count of the row pass (the number of LDS windows
-per update, i.e. row-pass blocks) using the library's HIP-event timing, keeps
-the fastest, and caches it in a JSON file keyed by the device name and the
+on each row path (fused row pass with each candidate band count, i.e. the
+number of LDS windows and row-pass blocks per update; or the split facet
+row pass + facet accumulate) using the library's HIP-event timing, keeps the
+fastest, and caches it in a JSON file keyed by the device name and the
 shape.  Cache: $SIMRADAR_TUNING_CACHE or ~/.cache/simradar/tuning.json.
 """
 from __future__ import annotations
@@ -13,6 +14,8 @@ import json
 import os
 
 CANDIDATE_BANDS = (64, 128, 256, 512)
+# (row path, band count) pairs timed; the split path has no band count
+PATH_FUSED, PATH_SPLIT = 1, 2
 
 
 def cache_path() -> str:
@@ -46,19 +49,27 @@ def _store(cache):
     os.replace(tmp, p)
 
 
+def _apply(sim, entry):
+    sim.set_row_path(entry["row_path"])
+    sim.set_row_bands(entry["row_bands"])
+
+
 def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
-    """Pick the band count of the fused row pass for this simulator's shape
-    and apply it.  Returns {"row_bands": n, "times_us": {...}}."""
+    """Pick the row path and the band count of the fused row pass for this
+    simulator's shape and apply them.  Returns {"row_path": p, "row_bands": n,
+    "times_us": {...}} (times per update of every candidate)."""
     import torch
     key = shape_key(sim)
     cache = _load() if use_cache else {}
-    if key in cache:
-        sim.set_row_bands(cache[key]["row_bands"])
+    if key in cache and "row_path" in cache[key]:
+        _apply(sim, cache[key])
         return cache[key]
     T = sim.empty_spectra(2)
     times = {}
     r = sim.radar
-    for nb in CANDIDATE_BANDS:
+    cands = [(PATH_FUSED, nb) for nb in CANDIDATE_BANDS] + [(PATH_SPLIT, 0)]
+    for path, nb in cands:
+        sim.set_row_path(path)
         sim.set_row_bands(nb)
         sim.update_and_accumulate(spec0, 0.0, 1, T)        # warm-up
         torch.cuda.synchronize()
@@ -68,10 +79,12 @@ def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
         prof = sim.profile_read()
         sim.profile(False)
         total = sum(ms for ms, n in prof.values())
-        times[nb] = 1e3 * total / repeats
+        times[(path, nb)] = 1e3 * total / repeats
     best = min(times, key=times.get)
-    sim.set_row_bands(best)
-    entry = {"row_bands": best, "times_us": {str(k): round(v, 1) for k, v in times.items()}}
+    entry = {"row_path": best[0], "row_bands": best[1],
+             "times_us": {("fused%d" % nb if p == PATH_FUSED else "split"): round(v, 1)
+                          for (p, nb), v in times.items()}}
+    _apply(sim, entry)
     if use_cache:
         cache = _load()
         cache[key] = entry

@@ -26,6 +26,7 @@ struct sim_ctx {
   void* ws;
   size_t ws_bytes;
   int row_bands;   // tuning: bands of the fused row pass (0 = default)
+  int row_path;    // tuning: row path of the fused call (SIM_ROW_PATH_*)
   bool capturing;  // a batch is being captured into a graph
   // per-kernel timing
   bool profiling;
@@ -114,12 +115,13 @@ RowPlan row_plan(int nx, size_t cs) {
   p.rpb = simk::row_rpb(l);
   p.threads = simk::row_threads(l);
   p.fft_bytes = simk::row_fft_lds(l, (int)cs);
+  p.front_bytes = p.fft_bytes + simk::row_stage_bytes(simk::row_stage_fused(l, (int)cs), l, (int)cs);
   p.acc_bytes = 0;
   return p;
 }
 
 struct WsLayout {
-  size_t planes, part, hdr, bandcnt, total;
+  size_t planes, part, hdr, bandcnt, facets, facet_stride, total;
 };
 
 WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
@@ -135,6 +137,10 @@ WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
   off = align256(off + (size_t)kMaxBands * kSlots * 16);
   L.bandcnt = off;
   off = align256(off + (size_t)kMaxBands * 8 * 4);
+  // facet fields of the split row path (9 planes of P reals)
+  L.facets = off;
+  L.facet_stride = align256(P * (cs / 2));
+  off += 9 * L.facet_stride;
   L.total = off;
   return L;
 }
@@ -295,9 +301,9 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   const ColPlan cp = col_plan(g->nx, g->ny, cs);
   if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
   RowPlan rpl = row_plan(g->nx, cs);
-  const int wk = window_bins(r->n_gates, r->n_doppler, cs, rpl.fft_bytes);
+  const int wk = window_bins(r->n_gates, r->n_doppler, cs, rpl.front_bytes);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
-  rpl.acc_bytes = rpl.fft_bytes + (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
+  rpl.acc_bytes = rpl.front_bytes + (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
   int target = rpl.threads <= 512 ? kMaxBands : kMaxBands / 2;
   if (c->row_bands > 0 && c->row_bands < target) target = c->row_bands;
   int n_bands, band_rows;
@@ -327,6 +333,43 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   if (s != SIM_OK) return s;
   ProfScope p(c, SIM_KERNEL_REDUCE_PARTIALS, st);
   return dev(simk::launch_reduce<Real>(rp, wp, Tj, (unsigned long long*)counters, st));
+}
+
+template <typename Real>
+sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
+                             const sim_radar* r, double t, int32_t j, void* t_fast,
+                             sim_counters* counters, int32_t* code, hipStream_t st,
+                             const WsLayout& L);
+
+// Row path of the fused call: the fused row pass (facets never leave the
+// chip), or the facet row pass into the workspace followed by the facet
+// accumulate.  Automatic choice: the fused row pass where its kernel keeps
+// the facet fields in registers without spilling (float, rows up to 4096).
+bool use_split(const sim_ctx* c, const sim_grid* g) {
+  if (c->row_path == SIM_ROW_PATH_FUSED) return false;
+  if (c->row_path == SIM_ROW_PATH_SPLIT) return true;
+  return c->prec == SIM_PREC_FP64 || g->nx > 4096;
+}
+
+template <typename Real>
+sim_status accumulate_split(sim_ctx* c, const sim_grid* g, const void* spec0, const sim_radar* r,
+                            double t, int32_t j, void* t_fast, sim_counters* counters,
+                            int32_t* code, hipStream_t st, const WsLayout& L) {
+  char* fb = (char*)c->ws + L.facets;
+  const size_t fs = L.facet_stride;
+  sim_facets f;
+  f.disp_x = fb + 0 * fs;
+  f.disp_y = fb + 1 * fs;
+  f.h = fb + 2 * fs;
+  f.sx = fb + 3 * fs;
+  f.sy = fb + 4 * fs;
+  f.jac = fb + 5 * fs;
+  f.ddisp_x = fb + 6 * fs;
+  f.ddisp_y = fb + 7 * fs;
+  f.dh = fb + 8 * fs;
+  const sim_status s = sim_surface_update(c, g, spec0, t, 1.0 / r->prf_hz, &f, st);
+  if (s != SIM_OK) return s;
+  return accumulate_facets<Real>(c, g, &f, r, t, j, t_fast, counters, code, st, L);
 }
 
 template <typename Real>
@@ -407,6 +450,7 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->profiling = false;
   c->used = 0;
   c->row_bands = 0;
+  c->row_path = SIM_ROW_PATH_AUTO;
   c->capturing = false;
   const size_t cs = csize(c);
   const size_t bytes = (size_t)simk::kTwEntries * cs;
@@ -538,11 +582,16 @@ sim_status sim_update_and_accumulate(sim_ctx* ctx, const sim_grid* grid, const v
   s = use_device(ctx);
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
+  const bool split = use_split(ctx, grid);
   if (ctx->prec == SIM_PREC_FP64)
-    return accumulate_fused<double>(ctx, grid, spec0, radar, t, j, t_fast, counters, facet_code,
-                                    st, L);
-  return accumulate_fused<float>(ctx, grid, spec0, radar, t, j, t_fast, counters, facet_code, st,
-                                 L);
+    return split ? accumulate_split<double>(ctx, grid, spec0, radar, t, j, t_fast, counters,
+                                            facet_code, st, L)
+                 : accumulate_fused<double>(ctx, grid, spec0, radar, t, j, t_fast, counters,
+                                            facet_code, st, L);
+  return split ? accumulate_split<float>(ctx, grid, spec0, radar, t, j, t_fast, counters,
+                                         facet_code, st, L)
+               : accumulate_fused<float>(ctx, grid, spec0, radar, t, j, t_fast, counters,
+                                         facet_code, st, L);
 }
 
 sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* t_fast,
@@ -671,6 +720,12 @@ sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
   if (key == SIM_TUNE_ROW_BANDS) {
     if (value < 0 || value > kMaxBands || (value & (value - 1)) != 0) return SIM_ERR_ARG;
     ctx->row_bands = value;
+    return SIM_OK;
+  }
+  if (key == SIM_TUNE_ROW_PATH) {
+    if (value != SIM_ROW_PATH_AUTO && value != SIM_ROW_PATH_FUSED && value != SIM_ROW_PATH_SPLIT)
+      return SIM_ERR_ARG;
+    ctx->row_path = value;
     return SIM_OK;
   }
   return SIM_ERR_ARG;

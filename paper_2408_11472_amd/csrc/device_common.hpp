@@ -156,10 +156,15 @@ struct FftPlan {
 // (b - j) * R + j + r * Ns, j = b mod Ns.  On the last stage those positions
 // coincide with the register slots, so the data stays in registers.  LDS
 // element i of the sequence lives at lds[lpad(i) * LS].
-template <typename T, int N, int E, int R, int Ns, bool LAST, int LS, int DIR>
+// Twiddles: with FULL == false, tw is the global table of slices (entry
+// M + m = e^{2 pi i m / M}); with FULL == true, tw holds the N entries
+// e^{2 pi i k / N} of this transform size (an LDS copy), and the size-M
+// slice is read with stride N / M.
+template <typename T, int N, int E, int R, int Ns, bool LAST, int LS, int DIR, bool FULL>
 __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid,
                                                const cplx<T>* __restrict__ tw) {
   constexpr int Tn = N / E;
+  constexpr int TS = FULL ? N / (Ns * R) : 1;     // stride of the slice in the table
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
     cplx<T> u[R];
@@ -172,8 +177,8 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid
       // from the size-(Ns R) slice of the table, the other powers are formed
       // with at most three products and applied at once, so no power is
       // kept live beyond its use.
-      const cplx<T>* twm = tw + Ns * R;
-      cplx<T> w1 = twm[(unsigned)j];
+      const cplx<T>* twm = FULL ? tw : tw + Ns * R;
+      cplx<T> w1 = twm[(unsigned)(j * TS)];
       if (DIR < 0) w1.y = -w1.y;
       const cplx<T> w2 = cmul(w1, w1);
       const cplx<T> w3 = cmul(w2, w1);
@@ -181,7 +186,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid
       if (R > 2) u[2] = cmul(u[2], w2);
       if (R > 3) u[3] = cmul(u[3], w3);
       if (R > 4) {
-        cplx<T> w4 = twm[(unsigned)(4 * j)];
+        cplx<T> w4 = twm[(unsigned)(4 * j * TS)];
         if (DIR < 0) w4.y = -w4.y;
         u[4] = cmul(u[4], w4);
         u[5] = cmul(u[5], cmul(w4, w1));
@@ -219,14 +224,14 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid
   }
 }
 
-template <typename T, int LOG2N, int E, int LS, int DIR, int S>
+template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL, int S>
 __device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, int tid,
                                            const cplx<T>* __restrict__ tw) {
   using P = FftPlan<LOG2N, E>;
   if constexpr (S < P::NSTAGES) {
-    stockham_stage<T, (1 << LOG2N), E, P::radix(S), P::ns(S), S == P::NSTAGES - 1, LS, DIR>(
-        v, lds, tid, tw);
-    fft_stages<T, LOG2N, E, LS, DIR, S + 1>(v, lds, tid, tw);
+    stockham_stage<T, (1 << LOG2N), E, P::radix(S), P::ns(S), S == P::NSTAGES - 1, LS, DIR,
+                   FULL>(v, lds, tid, tw);
+    fft_stages<T, LOG2N, E, LS, DIR, FULL, S + 1>(v, lds, tid, tw);
   }
 }
 
@@ -235,11 +240,11 @@ __device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, int tid,
 // per thread in slot order (slot m = position tid + m*N/E) on entry and on
 // exit.  lds points at this sequence's LDS region (lpad(N) elements, element
 // stride LS).  Every thread of the block must call it (barriers).
-template <typename T, int LOG2N, int E, int LS, int DIR>
+template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL = false>
 __device__ __forceinline__ void fft_seq(cplx<T>* v, cplx<T>* lds, int tid,
                                         const cplx<T>* __restrict__ tw) {
   static_assert((1 << LOG2N) >= E, "transform shorter than the values per thread");
-  fft_stages<T, LOG2N, E, LS, DIR, 0>(v, lds, tid, tw);
+  fft_stages<T, LOG2N, E, LS, DIR, FULL, 0>(v, lds, tid, tw);
 }
 
 // ---------------------------------------------------------------------------

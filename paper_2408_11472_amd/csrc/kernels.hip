@@ -197,18 +197,84 @@ __device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, i
   }
 }
 
+// Direct global -> LDS loads of row iy of a plane into S (nx elements in
+// column order), issued by the TPR threads of a single-row block: 16 bytes
+// per lane (two float or one double element, adjacent within a tile), or 4
+// bytes per lane for float planes in one-column tiles.  Completion is
+// awaited with the vector-memory counter and a barrier before S is read.
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void stage_row(const cplx<Real>* __restrict__ plane, int iy,
+                                          const GridP& gp, cplx<Real>* S, int tr) {
+  constexpr int nx = 1 << LOG2NX, TPR = nx / ER, W = TPR / 64;
+  constexpr int cs = sizeof(cplx<Real>);
+  const int lane = tr & 63, w = tr >> 6;
+  const int lw = gp.tlw, lh = gp.tlh;
+  const size_t rb = ((size_t)(iy >> lh) << (LOG2NX + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  if (cs == 16 || lw >= 1) {
+    constexpr int EPL = 16 / cs;       // elements per lane
+    constexpr int PER = 64 * EPL;      // elements per wave instruction
+#pragma unroll
+    for (int c = w; c < nx / PER; c += W) {
+      const int ix = c * PER + lane * EPL;
+      const cplx<Real>* src =
+          plane + rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1));
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr)(S + c * PER), 16, 0, 0);
+    }
+  } else {
+    const Real* f = reinterpret_cast<const Real*>(plane);
+#pragma unroll
+    for (int c = w; c < 2 * nx / 64; c += W) {
+      const int qf = c * 64 + lane;    // scalar index within the row
+      const int ix = qf >> 1;
+      const size_t e = rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1));
+      __builtin_amdgcn_global_load_lds((const void*)(f + 2 * e + (qf & 1)),
+                                       (lds_ptr)(reinterpret_cast<Real*>(S) + c * 64), 4, 0, 0);
+    }
+  }
+}
+
+// Where the next transform's row comes from (staged mode): plane index and
+// row, or no next transform (plane < 0).
+struct NextRow {
+  int plane, iy;
+};
+
 // Inverse transform along x of one plane for one row.  The thread
 // coordinate is made opaque per call, so that addresses and LDS offsets are
 // recomputed per transform instead of being kept live across all six.
-template <typename Real, int LOG2NX>
-__device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ plane, int iy,
-                                              bool valid, int tr, const GridP& gp,
-                                              cplx<Real>* lrow,
-                                              const cplx<Real>* __restrict__ tw, cplx<Real>* v) {
+// Staged mode: the row was loaded into S ahead of time; once every thread
+// has its values, the next transform's row is put in flight into S.
+template <typename Real, int LOG2NX, bool STAGE>
+__device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ planes, size_t psz,
+                                              int p, int iy, bool valid, int tr,
+                                              const GridP& gp, cplx<Real>* lrow, cplx<Real>* S,
+                                              NextRow nxt, const cplx<Real>* __restrict__ tw,
+                                              cplx<Real>* v) {
   int trv = tr;
   asm volatile("" : "+v"(trv));
-  load_row<Real, LOG2NX>(plane, iy, valid, trv, gp.tlw, gp.tlh, v);
-  fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
+  if constexpr (STAGE) {
+    constexpr int TPR = (1 << LOG2NX) / ER;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < ER; ++m) v[m] = S[trv + m * TPR];
+    __syncthreads();
+    if (nxt.plane >= 0) stage_row<Real, LOG2NX>(planes + (size_t)nxt.plane * psz, nxt.iy, gp, S, trv);
+    // tw: the LDS copy of the nx twiddles of this size (after S)
+    fft_seq<Real, LOG2NX, ER, 1, +1, true>(v, lrow, trv, S + (1 << LOG2NX));
+  } else {
+    load_row<Real, LOG2NX>(planes + (size_t)p * psz, iy, valid, trv, gp.tlw, gp.tlh, v);
+    fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
+  }
+}
+
+// LDS copy of the nx twiddles e^{2 pi i k / nx} (slice nx of the table).
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void load_row_twiddles(cplx<Real>* dst,
+                                                  const cplx<Real>* __restrict__ tw) {
+  constexpr int nx = 1 << LOG2NX;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) dst[i] = tw[nx + i];
 }
 
 // The nine facet quantities of one row, in the order they become available:
@@ -219,27 +285,30 @@ struct RowFacets {
   Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
 };
 
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, bool STAGE>
 __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes, size_t psz,
                                            int iy, bool valid, int tr, const GridP& gp,
-                                           cplx<Real>* lrow,
+                                           cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            const cplx<Real>* __restrict__ tw,
                                            RowFacets<Real>& F) {
   cplx<Real> v[ER];
   Real hx[ER], hy[ER], dxx[ER];
-  row_transform<Real, LOG2NX>(planes + 1 * psz, iy, valid, tr, gp, lrow, tw, v);  // Dy + i h_x
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
+                                     NextRow{2, iy_stage}, tw, v);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 2 * psz, iy, valid, tr, gp, lrow, tw, v);  // h_y + i Dx_x
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
+                                     NextRow{3, iy_stage}, tw, v);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     hy[m] = v[m].x;
     dxx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 3 * psz, iy, valid, tr, gp, lrow, tw, v);  // Dx_y + i Dy_y
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
+                                     NextRow{0, iy_stage}, tw, v);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     const Real dxy = v[m].x, dyy = v[m].y;
@@ -254,26 +323,30 @@ __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes
   }
 }
 
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, bool STAGE>
 __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
                                            int iy, bool valid, int tr, const GridP& gp,
-                                           cplx<Real>* lrow,
-                                           const cplx<Real>* __restrict__ tw,
+                                           cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
+                                           int iy_next, const cplx<Real>* __restrict__ tw,
                                            RowFacets<Real>& F) {
   cplx<Real> v[ER];
-  row_transform<Real, LOG2NX>(planes + 0 * psz, iy, valid, tr, gp, lrow, tw, v);  // h + i Dx
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
+                                     NextRow{4, iy_stage}, tw, v);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 4 * psz, iy, valid, tr, gp, lrow, tw, v);  // dh + i dDx
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
+                                     NextRow{5, iy_stage}, tw, v);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.dh[m] = v[m].x;
     F.dDx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX>(planes + 5 * psz, iy, valid, tr, gp, lrow, tw, v);  // dDy
+  // the row after this one starts with plane 1 (iy_next < 0: none)
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
+                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
 }
@@ -287,8 +360,13 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   constexpr int TPR = row_tpr(LOG2NX);
   constexpr int RPB = row_rpb(LOG2NX);
   const int ny = gp.ny;
+  // No staging here: the wait for a staged row (vector-memory counter) would
+  // also wait for this kernel's facet stores, which costs more than the load
+  // latency it hides.
+  constexpr bool STAGE = false;
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
+  cplx<Real>* S = nullptr;   // (no staging row)
   const size_t psz = (size_t)nx * ny;
   // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
   // contiguous run of row chunks, so that the chunks sharing a plane tile
@@ -296,11 +374,13 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   const int nblk = gridDim.x;
   const int q = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
                                 : blockIdx.x;
+
   for (int iy0 = q * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
+    const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB : -1;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
+    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -311,7 +391,8 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
         out.p[5][o] = F.jac[m];
       }
     }
-    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
+    row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
+                                    F);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -351,11 +432,14 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   constexpr int TPR = row_tpr(LOG2NX);
   constexpr int RPB = row_rpb(LOG2NX);
   const int ny = gp.ny;
+  constexpr bool STAGE = row_stage_fused(LOG2NX, sizeof(cplx<Real>));
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   const size_t fft_bytes = (size_t)RPB * lpad(nx) * sizeof(cplx<Real>);
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
+  cplx<Real>* S = reinterpret_cast<cplx<Real>*>(smem_raw + fft_bytes);
   const int band = blockIdx.x;
-  WinCtx<Real> w = win_ctx<Real>(smem_raw, fft_bytes, rp, wp, Tj, band);
+  WinCtx<Real> w = win_ctx<Real>(
+      smem_raw, fft_bytes + row_stage_bytes(STAGE, LOG2NX, sizeof(cplx<Real>)), rp, wp, Tj, band);
   win_init(w, rp, wp);
   uint32_t cnt[5] = {0, 0, 0, 0, 0};
   uint32_t overflow = 0;
@@ -383,13 +467,20 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   }
   const int row_begin = grouped ? first_tile_row * TH + member * RPB : band * wp.band_rows;
   const int row_end = grouped ? ny : min(ny, row_begin + wp.band_rows);
+  // staged rows are clamped into the grid (a row past the band end is
+  // transformed but not scattered)
+  if (STAGE) load_row_twiddles<Real, LOG2NX>(S + nx, tw);   // ordered by the first barrier
+  if (STAGE && n_steps > 0) stage_row<Real, LOG2NX>(planes + psz, min(row_begin, ny - 1), gp, S, tr);
   for (int k = 0; k < n_steps; ++k) {
     const int iy0 = row_begin + k * step_rows;
     const int iy = iy0 + rl;
     const bool valid = iy < row_end;
+    const int iy_stage = min(iy, ny - 1);
+    const int iy_next = k + 1 < n_steps ? min(iy0 + step_rows + rl, ny - 1) : -1;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
-    row_motion<Real, LOG2NX>(planes, psz, iy, valid, tr, gp, lrow, tw, F);
+    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, tw, F);
+    row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, iy_next,
+                                    tw, F);
     int key[ER];
     cplx<Real> cv[ER];
     // opaque row coordinates: the grid positions of the facets are
@@ -836,8 +927,10 @@ template <typename Real, int L>
 static hipError_t rowpass_facets_t(const void* planes, const GridP& gp, const FacetPtrs<Real>& fp,
                                    const void* tw, hipStream_t st) {
   const int blocks = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
+  constexpr int cs = sizeof(cplx<Real>);
   hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks), dim3(row_threads(L)),
-                     row_fft_lds(L, sizeof(cplx<Real>)), st, (const cplx<Real>*)planes,
+                     row_fft_lds(L, cs), st,
+                     (const cplx<Real>*)planes,
                      with_tiles<Real>(gp), fp, (const cplx<Real>*)tw);
   return hipGetLastError();
 }

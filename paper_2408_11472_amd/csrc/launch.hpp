@@ -71,6 +71,22 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
   return (size_t)row_rpb(log2nx) * lpad_c((size_t)1 << log2nx) * cs;
 }
 
+// Staging of the next plane row in LDS for the fused row pass (direct
+// global -> LDS loads while the current row transform runs), for single-row
+// blocks whose LDS allows it:
+// after the transform rows, one row of nx elements and the nx twiddles of the
+// row size (read from LDS, so that no global load of the transform has to
+// wait behind the staged row).  The fused kernel keeps room for a full
+// window of partial spectra.
+constexpr size_t kFusedFrontMax = 100 * 1024;
+__host__ __device__ constexpr size_t row_stage_bytes(bool stage, int log2nx, int cs) {
+  return stage ? ((size_t)2 * cs << log2nx) : 0;
+}
+__host__ __device__ constexpr bool row_stage_fused(int log2nx, int cs) {
+  return row_rpb(log2nx) == 1 &&
+         row_fft_lds(log2nx, cs) + row_stage_bytes(true, log2nx, cs) <= kFusedFrontMax;
+}
+
 struct ColPlan {
   int cpb;
   int threads;
@@ -81,7 +97,8 @@ struct RowPlan {
   int rpb;
   int threads;
   size_t fft_bytes;   // LDS of the row transforms
-  size_t acc_bytes;   // fft_bytes + window + state (fused kernel)
+  size_t front_bytes; // fft_bytes + staging row (fused kernel)
+  size_t acc_bytes;   // front_bytes + window + state (fused kernel)
 };
 
 hipError_t init_kernel_attributes(int lds_bytes);

@@ -53,6 +53,8 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_profile_enable", "sim_profile_read")
 
 SIM_TUNE_ROW_BANDS = 0
+SIM_TUNE_ROW_PATH = 1
+SIM_ROW_PATH_AUTO, SIM_ROW_PATH_FUSED, SIM_ROW_PATH_SPLIT = 0, 1, 2
 
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
                 "reduce_partials", "segments_to_iq", "adjoint", "clear")
@@ -413,6 +415,10 @@ class Simulator:
     def set_row_bands(self, n: int):
         """Blocks of the fused row pass (a power of two <= 512; 0 = default)."""
         sim_set_tuning(self.ctx, SIM_TUNE_ROW_BANDS, int(n))
+
+    def set_row_path(self, path: int):
+        """Row path of update_and_accumulate: SIM_ROW_PATH_AUTO, _FUSED or _SPLIT."""
+        sim_set_tuning(self.ctx, SIM_TUNE_ROW_PATH, int(path))
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop per-kernel event timing."""

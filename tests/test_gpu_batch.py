@@ -109,6 +109,37 @@ def test_band_count_changes_only_summation_order(prec, pcode, cdt, tol, tmp_path
     for o in outs[1:]:
         assert rel_l2(o, outs[0]) <= tol
     entry = autotune.tune(sim, spec, repeats=2)
-    assert entry["row_bands"] in autotune.CANDIDATE_BANDS
-    assert autotune.tune(sim, spec)["row_bands"] == entry["row_bands"]   # cached
+    assert entry["row_path"] in (autotune.PATH_FUSED, autotune.PATH_SPLIT)
+    if entry["row_path"] == autotune.PATH_FUSED:
+        assert entry["row_bands"] in autotune.CANDIDATE_BANDS
+    again = autotune.tune(sim, spec)                                       # cached
+    assert (again["row_path"], again["row_bands"]) == (entry["row_path"], entry["row_bands"])
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,pcode,cdt", [("fp64", 0, np.complex128), ("fp32", 1, np.complex64)])
+@pytest.mark.parametrize("which", ["tiny", "small_256"])
+def test_row_paths_agree(prec, pcode, cdt, which):
+    """The fused row pass and the split facet row pass + facet accumulate give
+    the same spectra and the same facet indices."""
+    from paper_2408_11472_amd import simradar
+    print_case("row paths", prec, which)
+    wl = workloads.small_256() if which == "small_256" else workloads.tiny(
+        nx=64, ny=32, spacing=2.0, n_gates=32, n_doppler=16, n_fast=16, n_updates=3)
+    spec = torch.as_tensor(_spec(wl).astype(cdt), device="cuda")
+    sim = simradar.Simulator(wl.grid, wl.radar, pcode)
+    out = {}
+    for path in (simradar.SIM_ROW_PATH_FUSED, simradar.SIM_ROW_PATH_SPLIT):
+        sim.set_row_path(path)
+        T = sim.empty_spectra(wl.n_spec)
+        code = torch.empty((wl.grid.ny, wl.grid.nx), dtype=torch.int32, device="cuda")
+        cnt = sim.counters()
+        sim.update_and_accumulate(spec, wl.update_time(2), 2, T, counters=cnt, facet_code=code)
+        torch.cuda.synchronize()
+        out[path] = (T.cpu().numpy(), code.cpu().numpy(), cnt.cpu().numpy())
+    (Tf, cf, nf), (Ts, cs_, ns) = out[simradar.SIM_ROW_PATH_FUSED], out[simradar.SIM_ROW_PATH_SPLIT]
+    n_diff = int((cf != cs_).sum())
+    assert n_diff <= (0 if prec == "fp64" else max(2, cf.size // 10000)), n_diff
+    assert rel_l2(Tf, Ts) <= (1e-12 if prec == "fp64" else 1e-5 + 3 * np.sqrt(2 * n_diff / cf.size))
+    assert int(nf[:5].sum()) == int(ns[:5].sum()) == wl.n_facets
     sim.close()
