@@ -33,15 +33,19 @@ METRIC = "facet-updates/s + simulated IQ pulses/s (FP32+FP64-phase vs FP64, same
 ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48,
                        "surface_rowpass": 48 + 36, "accumulate_facets": 36}
 
-# Counter measurements of the FP32 kernels on this workload (profiles/), valid
-# only for the kernel sources they were taken on: HBM bytes per launch from
-# FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), scaled by a 1 GiB copy, and VALU
-# wave-instructions per launch (SQ_INSTS_VALU).
+# Counter measurements of the kernels of both contexts on this workload
+# (profiles/), valid only for the kernel sources they were taken on: HBM bytes
+# per launch from FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), scaled by a 1 GiB
+# copy, and VALU wave-instructions per launch (SQ_INSTS_VALU).
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "d57a7c82bc842154",
-    "traffic_bytes": {"surface_colpass": 1434e6, "fused_rowpass": 808e6},
-    "valu_wave_instr": {"surface_colpass": 2.10e8, "fused_rowpass": 1.89e8},
+    "source_sha": "368c3a2788733303",
+    "fp32": {"traffic_bytes": {"surface_colpass": 1286e6, "fused_rowpass": 809e6},
+             "valu_wave_instr": {"surface_colpass": 1.87e8, "fused_rowpass": 1.74e8}},
+    "fp64": {"traffic_bytes": {"surface_colpass": 2243e6, "surface_rowpass": 2824e6,
+                               "accumulate_facets": 1210e6},
+             "valu_wave_instr": {"surface_colpass": 1.97e8, "surface_rowpass": 9.63e7,
+                                 "accumulate_facets": 9.82e7}},
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
 
@@ -63,8 +67,8 @@ def parse():
     p.add_argument("--workload", default="track_4096")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 context")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-autotune", action="store_true",
-                   help="keep the default band count of the fused row pass")
+    p.add_argument("--autotune", action="store_true",
+                   help="time the row paths and band counts first and run the fastest")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="before timing, copy a buffer of this size once (a plain copy kernel "
                         "of known traffic, to scale the HBM byte counters of a profiler run)")
@@ -93,7 +97,7 @@ def timed_steps(sim, spec_t, wl, steps, warmup, torch):
     return dt, prof, T, Y
 
 
-def roofline(prof, wl, bytes_scale, measured_ok):
+def roofline(prof, wl, bytes_scale, measured_ok, prec_name):
     """Dominant kernel against the HBM peak, from its event-timed launches."""
     best = max((k for k in ALG_BYTES_PER_FACET if prof[k][1]), key=lambda k: prof[k][0])
     ms, n = prof[best]
@@ -104,9 +108,10 @@ def roofline(prof, wl, bytes_scale, measured_ok):
            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
            "alg_bytes_per_launch": alg}
-    if measured_ok and bytes_scale == 1 and best in MEASURED["traffic_bytes"]:
-        out["traffic"] = MEASURED["traffic_bytes"][best]
-        valu = MEASURED["valu_wave_instr"][best]
+    m = MEASURED[prec_name]
+    if measured_ok and best in m["traffic_bytes"]:
+        out["traffic"] = m["traffic_bytes"][best]
+        valu = m["valu_wave_instr"][best]
         out["valu_issue"] = {"achieved": round(valu / avg_s / 1e9, 1),
                              "peak": VALU_PEAK_WAVE_INSTR_PER_S / 1e9,
                              "unit": "G wave-instr/s",
@@ -217,7 +222,7 @@ def main():
         sim = simradar.Simulator(g, wl.radar, prec)
         spec_t = torch.as_tensor(spec.astype(cdt), device="cuda")
         tuning = None
-        if not a.no_autotune:
+        if a.autotune:
             from paper_2408_11472_amd import autotune
             tuning = autotune.tune(sim, spec_t, use_cache=False)
         dt, prof, T, Y = timed_steps(sim, spec_t, wl, a.steps, a.warmup, torch)
@@ -227,7 +232,7 @@ def main():
             "facet_updates_per_s": wl.n_facets * wl.n_spec * a.steps / dt,
             "iq_pulses_per_s": wl.n_pulses * a.steps / dt,
             "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in prof.items() if v[1]},
-            "roofline": roofline(prof, wl, scale, measured_ok),
+            "roofline": roofline(prof, wl, scale, measured_ok, name),
             "finite": bool(torch.isfinite(torch.view_as_real(Y)).all().item()),
             "tuning": tuning,
         }
