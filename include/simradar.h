@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 1
+#define SIM_ABI_VERSION 2
 
 typedef enum sim_status {
   SIM_OK = 0,
@@ -205,6 +205,27 @@ sim_status sim_update_and_accumulate(sim_ctx *ctx, const sim_grid *grid,
                                      int32_t n_spec, sim_counters *counters,
                                      int32_t *facet_code, void *stream);
 
+/* The spectrum in the layout the surface transform's first (column) pass
+ * reads: for each strip of adjacent columns it works on, rows in order, the
+ * pair (c(k), c(-k)) of every column of the strip, so that each update reads
+ * it contiguously.  Same content as the FFT-order spectrum (Sec. II.A: the
+ * surface is synthesised from it at every update); made once per run.
+ *   spec0     [ny][nx] complex, FFT order, read only.
+ *   prepared  caller-owned device buffer of sim_prepared_spectrum_size bytes,
+ *             16-byte aligned, written; its layout depends on grid and
+ *             precision only. */
+sim_status sim_prepared_spectrum_size(const sim_ctx *ctx, const sim_grid *grid,
+                                      size_t *bytes);
+sim_status sim_prepare_spectrum(sim_ctx *ctx, const sim_grid *grid, const void *spec0,
+                                void *prepared, void *stream);
+
+/* sim_update_and_accumulate from a prepared spectrum (identical results). */
+sim_status sim_update_and_accumulate_prepared(sim_ctx *ctx, const sim_grid *grid,
+                                              const void *prepared, const sim_radar *radar,
+                                              double t, int32_t j, void *t_fast,
+                                              int32_t n_spec, sim_counters *counters,
+                                              int32_t *facet_code, void *stream);
+
 /* Post-processing of Sec. III.B: s_j[g][m] = sum_k T[j][g][k]
  * exp(+2 pi i k m / N) (unnormalised), then for every pulse x in
  * [0, (n_spec - 1) n_fast):
@@ -306,7 +327,7 @@ sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 #define SIM_KERNEL_REDUCE_PARTIALS 4      /* windows -> T_fast[j]                */
 #define SIM_KERNEL_SEGMENTS_TO_IQ 5       /* T_fast -> Y                         */
 #define SIM_KERNEL_ADJOINT 6              /* waveform loss and adjoint kernels   */
-#define SIM_KERNEL_CLEAR 7                /* clearing T_fast in a batch run      */
+#define SIM_KERNEL_PREPARE 7              /* spectrum preparation, batch clears  */
 #define SIM_KERNEL_KINDS 8
 
 typedef struct sim_kernel_times {

@@ -288,9 +288,10 @@ struct ProfScope {
 };
 
 template <typename Real>
-sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, const sim_radar* r,
-                            double t, int32_t j, void* t_fast, sim_counters* counters,
-                            int32_t* code, hipStream_t st, const WsLayout& L) {
+sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, bool prepared,
+                            const sim_radar* r, double t, int32_t j, void* t_fast,
+                            sim_counters* counters, int32_t* code, hipStream_t st,
+                            const WsLayout& L) {
   GridP gp;
   RadarP rp;
   fill_grid(g, gp);
@@ -322,7 +323,8 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, co
   sim_status s;
   {
     ProfScope p(c, SIM_KERNEL_SURFACE_COLPASS, st);
-    s = dev(simk::launch_colpass<Real>(spec0, planes, gp, t, 1.0 / r->prf_hz, c->tw, st));
+    s = dev(simk::launch_colpass<Real>(spec0, planes, gp, t, 1.0 / r->prf_hz, c->tw, prepared,
+                                       st));
   }
   if (s != SIM_OK) return s;
   {
@@ -351,10 +353,15 @@ bool use_split(const sim_ctx* c, const sim_grid* g) {
   return c->prec == SIM_PREC_FP64 || g->nx > 4096;
 }
 
+sim_status surface_update_impl(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
+                               bool prepared, double t, double dt_pair, const sim_facets* out,
+                               hipStream_t st);
+
 template <typename Real>
-sim_status accumulate_split(sim_ctx* c, const sim_grid* g, const void* spec0, const sim_radar* r,
-                            double t, int32_t j, void* t_fast, sim_counters* counters,
-                            int32_t* code, hipStream_t st, const WsLayout& L) {
+sim_status accumulate_split(sim_ctx* c, const sim_grid* g, const void* spec0, bool prepared,
+                            const sim_radar* r, double t, int32_t j, void* t_fast,
+                            sim_counters* counters, int32_t* code, hipStream_t st,
+                            const WsLayout& L) {
   char* fb = (char*)c->ws + L.facets;
   const size_t fs = L.facet_stride;
   sim_facets f;
@@ -367,7 +374,7 @@ sim_status accumulate_split(sim_ctx* c, const sim_grid* g, const void* spec0, co
   f.ddisp_x = fb + 6 * fs;
   f.ddisp_y = fb + 7 * fs;
   f.dh = fb + 8 * fs;
-  const sim_status s = sim_surface_update(c, g, spec0, t, 1.0 / r->prf_hz, &f, st);
+  const sim_status s = surface_update_impl(c, g, spec0, prepared, t, 1.0 / r->prf_hz, &f, st);
   if (s != SIM_OK) return s;
   return accumulate_facets<Real>(c, g, &f, r, t, j, t_fast, counters, code, st, L);
 }
@@ -521,6 +528,60 @@ sim_status sim_set_workspace(sim_ctx* ctx, void* device_ptr, size_t bytes) {
   return SIM_OK;
 }
 
+namespace {
+
+sim_status surface_update_impl(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
+                               bool prepared, double t, double dt_pair, const sim_facets* out,
+                               hipStream_t st) {
+  GridP gp;
+  fill_grid(grid, gp);
+  const size_t cs = csize(ctx);
+  const ColPlan cp = col_plan(grid->nx, grid->ny, cs);
+  if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
+  void* const o[9] = {out->disp_x, out->disp_y, out->h, out->sx, out->sy, out->jac,
+                      out->ddisp_x, out->ddisp_y, out->dh};
+  void* planes = ctx->ws;
+  const bool f64 = ctx->prec == SIM_PREC_FP64;
+  sim_status s;
+  {
+    ProfScope p(ctx, SIM_KERNEL_SURFACE_COLPASS, st);
+    s = f64 ? dev(simk::launch_colpass<double>(spec0, planes, gp, t, dt_pair, ctx->tw, prepared,
+                                               st))
+            : dev(simk::launch_colpass<float>(spec0, planes, gp, t, dt_pair, ctx->tw, prepared,
+                                              st));
+  }
+  if (s != SIM_OK) return s;
+  ProfScope p(ctx, SIM_KERNEL_SURFACE_ROWPASS, st);
+  return f64 ? dev(simk::launch_rowpass_facets<double>(planes, gp, o, ctx->tw, st))
+             : dev(simk::launch_rowpass_facets<float>(planes, gp, o, ctx->tw, st));
+}
+
+sim_status update_and_accumulate_impl(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
+                                      bool prepared, const sim_radar* radar, double t, int32_t j,
+                                      void* t_fast, int32_t n_spec, sim_counters* counters,
+                                      int32_t* facet_code, void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, radar, &L);
+  if (s != SIM_OK) return s;
+  if (!spec0 || !t_fast || !isfin(t)) return SIM_ERR_ARG;
+  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const bool split = use_split(ctx, grid);
+  if (ctx->prec == SIM_PREC_FP64)
+    return split ? accumulate_split<double>(ctx, grid, spec0, prepared, radar, t, j, t_fast,
+                                            counters, facet_code, st, L)
+                 : accumulate_fused<double>(ctx, grid, spec0, prepared, radar, t, j, t_fast,
+                                            counters, facet_code, st, L);
+  return split ? accumulate_split<float>(ctx, grid, spec0, prepared, radar, t, j, t_fast,
+                                         counters, facet_code, st, L)
+               : accumulate_fused<float>(ctx, grid, spec0, prepared, radar, t, j, t_fast,
+                                         counters, facet_code, st, L);
+}
+
+}  // namespace
+
 sim_status sim_surface_update(sim_ctx* ctx, const sim_grid* grid, const void* spec0, double t,
                               double dt_pair, const sim_facets* out, void* stream) {
   WsLayout L;
@@ -529,25 +590,32 @@ sim_status sim_surface_update(sim_ctx* ctx, const sim_grid* grid, const void* sp
   if (!spec0 || !facets_ok(out) || !isfin(t) || !isfin(dt_pair)) return SIM_ERR_ARG;
   s = use_device(ctx);
   if (s != SIM_OK) return s;
+  return surface_update_impl(ctx, grid, spec0, false, t, dt_pair, out, (hipStream_t)stream);
+}
+
+sim_status sim_prepared_spectrum_size(const sim_ctx* ctx, const sim_grid* grid, size_t* bytes) {
+  if (!ctx || !bytes) return SIM_ERR_ARG;
+  const sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  *bytes = 2 * (size_t)grid->nx * grid->ny * csize(ctx);
+  return SIM_OK;
+}
+
+sim_status sim_prepare_spectrum(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
+                                void* prepared, void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  if (!spec0 || !prepared || ((uintptr_t)prepared & 15) != 0) return SIM_ERR_ARG;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
   GridP gp;
   fill_grid(grid, gp);
-  const size_t cs = csize(ctx);
-  const ColPlan cp = col_plan(grid->nx, grid->ny, cs);
-  if (cp.lds_bytes > kLdsBudget) return SIM_ERR_UNSUPPORTED;
-  void* const o[9] = {out->disp_x, out->disp_y, out->h, out->sx, out->sy, out->jac,
-                      out->ddisp_x, out->ddisp_y, out->dh};
   hipStream_t st = (hipStream_t)stream;
-  void* planes = ctx->ws;
-  const bool f64 = ctx->prec == SIM_PREC_FP64;
-  {
-    ProfScope p(ctx, SIM_KERNEL_SURFACE_COLPASS, st);
-    s = f64 ? dev(simk::launch_colpass<double>(spec0, planes, gp, t, dt_pair, ctx->tw, st))
-            : dev(simk::launch_colpass<float>(spec0, planes, gp, t, dt_pair, ctx->tw, st));
-  }
-  if (s != SIM_OK) return s;
-  ProfScope p(ctx, SIM_KERNEL_SURFACE_ROWPASS, st);
-  return f64 ? dev(simk::launch_rowpass_facets<double>(planes, gp, o, ctx->tw, st))
-             : dev(simk::launch_rowpass_facets<float>(planes, gp, o, ctx->tw, st));
+  ProfScope p(ctx, SIM_KERNEL_PREPARE, st);
+  return ctx->prec == SIM_PREC_FP64
+             ? dev(simk::launch_prepare_spectrum<double>(spec0, prepared, gp, st))
+             : dev(simk::launch_prepare_spectrum<float>(spec0, prepared, gp, st));
 }
 
 sim_status sim_range_doppler_accumulate(sim_ctx* ctx, const sim_grid* grid,
@@ -574,24 +642,17 @@ sim_status sim_update_and_accumulate(sim_ctx* ctx, const sim_grid* grid, const v
                                      const sim_radar* radar, double t, int32_t j, void* t_fast,
                                      int32_t n_spec, sim_counters* counters,
                                      int32_t* facet_code, void* stream) {
-  WsLayout L;
-  sim_status s = common_checks(ctx, grid, radar, &L);
-  if (s != SIM_OK) return s;
-  if (!spec0 || !t_fast || !isfin(t)) return SIM_ERR_ARG;
-  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
-  s = use_device(ctx);
-  if (s != SIM_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  const bool split = use_split(ctx, grid);
-  if (ctx->prec == SIM_PREC_FP64)
-    return split ? accumulate_split<double>(ctx, grid, spec0, radar, t, j, t_fast, counters,
-                                            facet_code, st, L)
-                 : accumulate_fused<double>(ctx, grid, spec0, radar, t, j, t_fast, counters,
-                                            facet_code, st, L);
-  return split ? accumulate_split<float>(ctx, grid, spec0, radar, t, j, t_fast, counters,
-                                         facet_code, st, L)
-               : accumulate_fused<float>(ctx, grid, spec0, radar, t, j, t_fast, counters,
-                                         facet_code, st, L);
+  return update_and_accumulate_impl(ctx, grid, spec0, false, radar, t, j, t_fast, n_spec,
+                                    counters, facet_code, stream);
+}
+
+sim_status sim_update_and_accumulate_prepared(sim_ctx* ctx, const sim_grid* grid,
+                                              const void* prepared, const sim_radar* radar,
+                                              double t, int32_t j, void* t_fast, int32_t n_spec,
+                                              sim_counters* counters, int32_t* facet_code,
+                                              void* stream) {
+  return update_and_accumulate_impl(ctx, grid, prepared, true, radar, t, j, t_fast, n_spec,
+                                    counters, facet_code, stream);
 }
 
 sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* t_fast,
@@ -766,6 +827,7 @@ struct sim_batch {
   std::vector<sim_grid> grids;
   std::vector<sim_radar> radars;
   std::vector<int32_t> updates;
+  std::vector<size_t> prep_off;   // prepared spectrum of each member in the workspace
   size_t ws_bytes;
   // captured graph and the pointers it was captured with
   hipGraphExec_t exec;
@@ -786,8 +848,14 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
   for (int r = 0; r < R; ++r) {
     const sim_radar& rr = b->radars[r];
     const size_t n = (size_t)(b->updates[r] + 1) * rr.n_gates * rr.n_doppler;
-    ProfScope p(c, SIM_KERNEL_CLEAR, st);
+    ProfScope p(c, SIM_KERNEL_PREPARE, st);
     const sim_status s = dev(simk::launch_clear(t_fast[r], n * cs, st));
+    if (s != SIM_OK) return s;
+  }
+  // each member's spectrum in the column-pass layout, once per run
+  for (int r = 0; r < R; ++r) {
+    const sim_status s = sim_prepare_spectrum(c, &b->grids[r], spec0[r],
+                                              (char*)c->ws + b->prep_off[r], st);
     if (s != SIM_OK) return s;
   }
   for (int j = 0; j <= jmax; ++j) {
@@ -795,9 +863,9 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
       if (j > b->updates[r]) continue;
       const sim_radar& rr = b->radars[r];
       const double t = ((double)j * rr.n_fast) / rr.prf_hz;
-      const sim_status s = sim_update_and_accumulate(c, &b->grids[r], spec0[r], &rr, t, j,
-                                                     t_fast[r], b->updates[r] + 1, nullptr,
-                                                     nullptr, st);
+      const sim_status s = sim_update_and_accumulate_prepared(
+          c, &b->grids[r], (char*)c->ws + b->prep_off[r], &rr, t, j, t_fast[r],
+          b->updates[r] + 1, nullptr, nullptr, st);
       if (s != SIM_OK) return s;
     }
   }
@@ -840,6 +908,14 @@ sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
   b->grids.assign(grids, grids + n_real);
   b->radars.assign(radars, radars + n_real);
   b->updates.assign(n_updates, n_updates + n_real);
+  // members share the largest per-call layout; their prepared spectra follow
+  ws = align256(ws);
+  for (int r = 0; r < n_real; ++r) {
+    size_t pb = 0;
+    (void)sim_prepared_spectrum_size(ctx, &grids[r], &pb);
+    b->prep_off.push_back(ws);
+    ws = align256(ws + pb);
+  }
   b->ws_bytes = ws;
   b->have_graph = false;
   b->graph_stream = nullptr;

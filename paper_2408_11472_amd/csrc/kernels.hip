@@ -28,7 +28,11 @@ namespace simk {
 //   3: Dx_y + i Dy_y  4: dh + i dDx     5: dDy
 // Each column strip is handled by two blocks: group 0 makes planes 0-3 from
 // zeta, group 1 planes 4-5 from dzeta, so a thread keeps one spectral state.
-template <typename Real, int LOG2NY>
+// PREP: spec is the prepared spectrum (prepare_spectrum_kernel): per column
+// strip, rows in order, the pair (c(k), c(-k)) of each column of the strip,
+// so the loads of a wave are one contiguous run instead of CPB-element
+// pieces of rows and their mirrors.
+template <typename Real, int LOG2NY, bool PREP>
 __global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
 colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
                double t, double dt, const cplx<Real>* __restrict__ tw) {
@@ -66,8 +70,15 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
     const bool skip = (ix == nx / 2) || (iy == ny / 2) || (ix == 0 && iy == 0);
     cplx<Real> z = mk<Real>(0, 0);
     if (!skip) {
-      const cplx<Real> h0 = spec[(size_t)iy * nx + ix];
-      const cplx<Real> hm = spec[(size_t)my * nx + mx];
+      cplx<Real> h0, hm;
+      if constexpr (PREP) {
+        const cplx<Real>* pp = spec + 2 * (((size_t)strip * ny + iy) * CPB + c);
+        h0 = pp[0];
+        hm = pp[1];
+      } else {
+        h0 = spec[(size_t)iy * nx + ix];
+        hm = spec[(size_t)my * nx + mx];
+      }
       const double ky = dky * (double)nys;
       // w = sqrt(g) (kx^2 + ky^2)^(1/4): two reciprocal square roots refined
       // by Newton steps in double from the float estimate
@@ -165,6 +176,26 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
             ((iy & ((1 << LH) - 1)) << LW) + cw] = v[m];
       }
     }
+  }
+}
+
+// The prepared spectrum of the column pass: element (iy, ix) of the
+// FFT-order spectrum and its mirror (-iy, -ix) side by side, at position
+// (strip ny + iy) CPB + c for ix = strip CPB + c.  One thread per element,
+// rows read in order.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+prepare_spectrum_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ out, int nx,
+                        int ny, int cpb) {
+  const size_t n = (size_t)nx * ny;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int iy = (int)(i / nx), ix = (int)(i % nx);
+    const int my = (ny - iy) & (ny - 1), mx = (nx - ix) & (nx - 1);
+    const int strip = ix / cpb, c = ix % cpb;
+    cplx<Real>* o = out + 2 * (((size_t)strip * ny + iy) * cpb + c);
+    o[0] = spec[i];
+    o[1] = spec[(size_t)my * nx + mx];
   }
 }
 
@@ -898,29 +929,45 @@ static GridP with_tiles(const GridP& gp) {
 
 template <typename Real, int L>
 static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, double t, double dt,
-                            const void* tw, hipStream_t st) {
+                            const void* tw, bool prepared, hipStream_t st) {
   constexpr int cs = sizeof(cplx<Real>);
   if constexpr (col_lds(L, cs) > kLdsBudget) {
     return hipErrorInvalidValue;
   } else {
     const int strips = gp.nx / col_cpb(L, cs);
-    hipLaunchKernelGGL((colpass_kernel<Real, L>), dim3(2 * strips), dim3(col_threads(L, cs)),
-                       col_lds(L, cs), st, (const cplx<Real>*)spec, (cplx<Real>*)planes,
-                       with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
+    if (prepared)
+      hipLaunchKernelGGL((colpass_kernel<Real, L, true>), dim3(2 * strips),
+                         dim3(col_threads(L, cs)), col_lds(L, cs), st, (const cplx<Real>*)spec,
+                         (cplx<Real>*)planes, with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
+    else
+      hipLaunchKernelGGL((colpass_kernel<Real, L, false>), dim3(2 * strips),
+                         dim3(col_threads(L, cs)), col_lds(L, cs), st, (const cplx<Real>*)spec,
+                         (cplx<Real>*)planes, with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
     return hipGetLastError();
   }
 }
 
 template <typename Real>
 hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
-                          const void* tw, hipStream_t st) {
+                          const void* tw, bool prepared, hipStream_t st) {
   switch (gp.log2ny) {
 #define SIMK_CASE(L) \
-  case L: return colpass_t<Real, L>(spec, planes, gp, t, dt, tw, st);
+  case L: return colpass_t<Real, L>(spec, planes, gp, t, dt, tw, prepared, st);
     SIMK_COL_SIZES(SIMK_CASE)
 #undef SIMK_CASE
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename Real>
+hipError_t launch_prepare_spectrum(const void* spec, void* out, const GridP& gp, hipStream_t st) {
+  const int cpb = col_cpb(gp.log2ny, sizeof(cplx<Real>));
+  const size_t n = (size_t)gp.nx * gp.ny;
+  const size_t want = (n + 255) / 256;
+  const int blocks = (int)(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(prepare_spectrum_kernel<Real>, dim3(blocks), dim3(256), 0, st,
+                     (const cplx<Real>*)spec, (cplx<Real>*)out, gp.nx, gp.ny, cpb);
+  return hipGetLastError();
 }
 
 template <typename Real, int L>
@@ -1083,8 +1130,10 @@ static hipError_t set_attributes(int lds) {
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   };
 #define SIMK_CASE(L)                                                                           \
-  if constexpr (col_lds(L, sizeof(cplx<Real>)) <= kLdsBudget)                                  \
-    set((const void*)colpass_kernel<Real, L>);
+  if constexpr (col_lds(L, sizeof(cplx<Real>)) <= kLdsBudget) {                                \
+    set((const void*)colpass_kernel<Real, L, false>);                                          \
+    set((const void*)colpass_kernel<Real, L, true>);                                           \
+  }
   SIMK_COL_SIZES(SIMK_CASE)
 #undef SIMK_CASE
 #define SIMK_CASE(L)                                   \
@@ -1107,7 +1156,8 @@ hipError_t init_kernel_attributes(int lds) {
 
 #define SIMK_INSTANTIATE(R)                                                                      \
   template hipError_t launch_colpass<R>(const void*, void*, const GridP&, double, double,       \
-                                        const void*, hipStream_t);                              \
+                                        const void*, bool, hipStream_t);                        \
+  template hipError_t launch_prepare_spectrum<R>(const void*, void*, const GridP&, hipStream_t); \
   template hipError_t launch_rowpass_facets<R>(const void*, const GridP&, void* const*,         \
                                                const void*, hipStream_t);                       \
   template hipError_t launch_rowpass_accumulate<R>(const void*, const GridP&, const RadarP&,     \

@@ -106,7 +106,9 @@ hipError_t launch_clear(void* p, size_t bytes, hipStream_t st);
 
 template <typename Real>
 hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, double t, double dt,
-                          const void* tw, hipStream_t st);
+                          const void* tw, bool prepared, hipStream_t st);
+template <typename Real>
+hipError_t launch_prepare_spectrum(const void* spec, void* out, const GridP& gp, hipStream_t st);
 template <typename Real>
 hipError_t launch_rowpass_facets(const void* planes, const GridP& gp, void* const* out,
                                  const void* tw, hipStream_t st);

@@ -45,7 +45,8 @@ FACET_FIELDS = ("disp_x", "disp_y", "h", "sx", "sy", "jac",
 EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_get_precision", "sim_workspace_size", "sim_set_workspace",
             "sim_surface_update", "sim_range_doppler_accumulate",
-            "sim_update_and_accumulate", "sim_segments_to_iq",
+            "sim_update_and_accumulate", "sim_prepared_spectrum_size", "sim_prepare_spectrum",
+            "sim_update_and_accumulate_prepared", "sim_segments_to_iq",
             "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
             "sim_range_doppler_accumulate_adjoint",
             "sim_batch_create", "sim_batch_destroy", "sim_batch_workspace_size",
@@ -57,7 +58,7 @@ SIM_TUNE_ROW_PATH = 1
 SIM_ROW_PATH_AUTO, SIM_ROW_PATH_FUSED, SIM_ROW_PATH_SPLIT = 0, 1, 2
 
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
-                "reduce_partials", "segments_to_iq", "adjoint", "clear")
+                "reduce_partials", "segments_to_iq", "adjoint", "prepare")
 
 
 class sim_grid(ctypes.Structure):
@@ -110,6 +111,12 @@ _sig = {
     "sim_update_and_accumulate": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P,
                                                  ctypes.POINTER(sim_radar), _D, _I, _P, _I,
                                                  _P, _P, _P]),
+    "sim_prepared_spectrum_size": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid),
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "sim_prepare_spectrum": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P, _P, _P]),
+    "sim_update_and_accumulate_prepared": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P,
+                                                          ctypes.POINTER(sim_radar), _D, _I, _P,
+                                                          _I, _P, _P, _P]),
     "sim_segments_to_iq": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P]),
     "sim_waveform_loss": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P, _P, _P]),
     "sim_waveform_loss_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P,
@@ -200,6 +207,26 @@ def sim_update_and_accumulate(ctx, grid, spec0_ptr, radar, t, j, t_fast_ptr, n_s
            _lib.sim_update_and_accumulate(ctx, ctypes.byref(grid), spec0_ptr,
                                           ctypes.byref(radar), t, j, t_fast_ptr, n_spec,
                                           counters_ptr, code_ptr, stream))
+
+
+def sim_prepared_spectrum_size(ctx, grid) -> int:
+    n = ctypes.c_size_t(0)
+    _check("sim_prepared_spectrum_size",
+           _lib.sim_prepared_spectrum_size(ctx, ctypes.byref(grid), ctypes.byref(n)))
+    return n.value
+
+
+def sim_prepare_spectrum(ctx, grid, spec0_ptr, prepared_ptr, stream) -> None:
+    _check("sim_prepare_spectrum",
+           _lib.sim_prepare_spectrum(ctx, ctypes.byref(grid), spec0_ptr, prepared_ptr, stream))
+
+
+def sim_update_and_accumulate_prepared(ctx, grid, prepared_ptr, radar, t, j, t_fast_ptr, n_spec,
+                                       counters_ptr, code_ptr, stream) -> None:
+    _check("sim_update_and_accumulate_prepared",
+           _lib.sim_update_and_accumulate_prepared(ctx, ctypes.byref(grid), prepared_ptr,
+                                                   ctypes.byref(radar), t, j, t_fast_ptr, n_spec,
+                                                   counters_ptr, code_ptr, stream))
 
 
 def sim_segments_to_iq(ctx, radar, t_fast_ptr, n_spec, y_ptr, stream) -> None:
@@ -397,6 +424,34 @@ class Simulator:
                                                        (g.ny, g.nx), "facet_code"),
             self._stream(stream))
 
+    def prepare_spectrum(self, spec0, stream=None):
+        """The spectrum in the column-pass layout (a complex tensor of 2 nx ny
+        elements), for update_and_accumulate_prepared."""
+        g = self.grid
+        n = sim_prepared_spectrum_size(self.ctx, g) // (16 if self.precision == SIM_PREC_FP64
+                                                         else 8)
+        out = self.torch.empty(n, dtype=self.complex_dtype, device=self.device)
+        sim_prepare_spectrum(self.ctx, g,
+                             self._need(spec0, self.complex_dtype, (g.ny, g.nx), "spec0"),
+                             out.data_ptr(), self._stream(stream))
+        return out
+
+    def update_and_accumulate_prepared(self, prepared, t, j, t_fast, counters=None,
+                                       facet_code=None, stream=None):
+        n_spec = t_fast.shape[0]
+        r = self.radar
+        g = self.grid
+        sim_update_and_accumulate_prepared(
+            self.ctx, self.grid,
+            self._need(prepared, self.complex_dtype, (2 * g.nx * g.ny,), "prepared"),
+            self.radar, float(t), int(j),
+            self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
+            n_spec,
+            None if counters is None else self._need(counters, self.torch.int64, (6,), "counters"),
+            None if facet_code is None else self._need(facet_code, self.torch.int32,
+                                                       (g.ny, g.nx), "facet_code"),
+            self._stream(stream))
+
     def segments_to_iq(self, t_fast, y=None, stream=None):
         r = self.radar
         n_spec = t_fast.shape[0]
@@ -483,13 +538,18 @@ class Simulator:
             n_spec, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), self._stream(stream))
         return {"h": out[0], "sx": out[1], "sy": out[2]}
 
-    def run(self, spec0, n_updates, t_fast=None, y=None, counters=None, stream=None):
-        """Algorithm 1 and post-processing: U + 1 spectra, then Y."""
+    def run(self, spec0, n_updates, t_fast=None, y=None, counters=None, stream=None,
+            prepared=None):
+        """Algorithm 1 and post-processing: U + 1 spectra, then Y.  The
+        spectrum is put in the column-pass layout once (or ``prepared`` is
+        used as it is)."""
         t_fast = t_fast if t_fast is not None else self.empty_spectra(n_updates + 1)
         r = self.radar
+        prep = prepared if prepared is not None else self.prepare_spectrum(spec0, stream=stream)
         for j in range(n_updates + 1):
             t = (j * r.n_fast) / r.prf_hz
-            self.update_and_accumulate(spec0, t, j, t_fast, counters=counters, stream=stream)
+            self.update_and_accumulate_prepared(prep, t, j, t_fast, counters=counters,
+                                                stream=stream)
         return t_fast, self.segments_to_iq(t_fast, y, stream=stream)
 
 

@@ -31,7 +31,10 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     from paper_2408_11472_amd import simradar
-    assert simradar.sim_abi_version() == 1
+    import re
+    with open(HEADER) as f:
+        declared = int(re.search(r"#define SIM_ABI_VERSION (\d+)", f.read()).group(1))
+    assert simradar.sim_abi_version() == declared
     assert simradar.sim_status_string(0) == "ok"
     assert "workspace" in simradar.sim_status_string(4)
 

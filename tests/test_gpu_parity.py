@@ -285,3 +285,34 @@ def test_full_run_small_256(prec, pcode, npdt):
         sim.range_doppler_accumulate(fac, t, j, T3)
     torch.cuda.synchronize()
     assert rel_l2(T3.cpu().numpy(), T.cpu().numpy()) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec,pcode,npdt", PRECS)
+@pytest.mark.parametrize("nx,ny", [(64, 32), (256, 256), (8192, 32), (32, 16384), (1024, 64)])
+def test_prepared_spectrum_gives_the_same_update(prec, pcode, npdt, nx, ny):
+    """The column pass reading the prepared spectrum computes exactly what it
+    computes from the FFT-order spectrum."""
+    if prec == "fp64" and ny > 8192:
+        pytest.skip("ny > 8192 is float-only (LDS of one column)")
+    simradar = _sim()
+    print_case("prepared", prec, nx, ny)
+    wl = workloads.tiny(nx=nx, ny=ny, spacing=1.0, n_gates=32, n_doppler=16, n_fast=16,
+                        n_updates=3, seed=nx * 3 + ny)
+    wl.sea.swh = min(wl.sea.swh, wl.sea.peak_wavelength / 60.0)
+    spec = _spec(wl)
+    sim = simradar.Simulator(wl.grid, wl.radar, pcode)
+    spec_t = torch.as_tensor(spec.astype(np.complex64 if npdt == np.float32 else np.complex128),
+                             device="cuda")
+    prep = sim.prepare_spectrum(spec_t)
+    out = []
+    for use_prep in (False, True):
+        T = sim.empty_spectra(wl.n_spec)
+        code = torch.empty((ny, nx), dtype=torch.int32, device="cuda")
+        if use_prep:
+            sim.update_and_accumulate_prepared(prep, wl.update_time(2), 2, T, facet_code=code)
+        else:
+            sim.update_and_accumulate(spec_t, wl.update_time(2), 2, T, facet_code=code)
+        torch.cuda.synchronize()
+        out.append((T.cpu().numpy(), code.cpu().numpy()))
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert rel_l2(out[1][0], out[0][0]) <= (1e-13 if prec == "fp64" else 1e-6)
