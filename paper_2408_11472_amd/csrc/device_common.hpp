@@ -160,9 +160,15 @@ struct FftPlan {
 // M + m = e^{2 pi i m / M}); with FULL == true, tw holds the N entries
 // e^{2 pi i k / N} of this transform size (an LDS copy), and the size-M
 // slice is read with stride N / M.
-template <typename T, int N, int E, int R, int Ns, bool LAST, int LS, int DIR, bool FULL>
-__device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid,
+// PP (ping-pong): exchanges alternate between lds and lds2 (stage parity
+// SI), so a stage's reads need no closing barrier: the next stage writes the
+// other buffer, and the one after that is behind the next stage's barrier.
+// The caller separates consecutive transforms by a barrier.
+template <typename T, int N, int E, int R, int Ns, bool LAST, int LS, int DIR, bool FULL,
+          bool PP, int SI>
+__device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds0, cplx<T>* lds2, int tid,
                                                const cplx<T>* __restrict__ tw) {
+  cplx<T>* lds = (PP && (SI & 1)) ? lds2 : lds0;
   constexpr int Tn = N / E;
   constexpr int TS = FULL ? N / (Ns * R) : 1;     // stride of the slice in the table
 #pragma unroll
@@ -220,18 +226,18 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* v, cplx<T>* lds, int tid
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = lds[lpad(tid + m * Tn) * LS];
-    __syncthreads();
+    if (!PP) __syncthreads();
   }
 }
 
-template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL, int S>
-__device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, int tid,
+template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL, bool PP, int S>
+__device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, cplx<T>* lds2, int tid,
                                            const cplx<T>* __restrict__ tw) {
   using P = FftPlan<LOG2N, E>;
   if constexpr (S < P::NSTAGES) {
     stockham_stage<T, (1 << LOG2N), E, P::radix(S), P::ns(S), S == P::NSTAGES - 1, LS, DIR,
-                   FULL>(v, lds, tid, tw);
-    fft_stages<T, LOG2N, E, LS, DIR, FULL, S + 1>(v, lds, tid, tw);
+                   FULL, PP, S>(v, lds, lds2, tid, tw);
+    fft_stages<T, LOG2N, E, LS, DIR, FULL, PP, S + 1>(v, lds, lds2, tid, tw);
   }
 }
 
@@ -240,11 +246,12 @@ __device__ __forceinline__ void fft_stages(cplx<T>* v, cplx<T>* lds, int tid,
 // per thread in slot order (slot m = position tid + m*N/E) on entry and on
 // exit.  lds points at this sequence's LDS region (lpad(N) elements, element
 // stride LS).  Every thread of the block must call it (barriers).
-template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL = false>
+template <typename T, int LOG2N, int E, int LS, int DIR, bool FULL = false, bool PP = false>
 __device__ __forceinline__ void fft_seq(cplx<T>* v, cplx<T>* lds, int tid,
-                                        const cplx<T>* __restrict__ tw) {
+                                        const cplx<T>* __restrict__ tw,
+                                        cplx<T>* lds2 = nullptr) {
   static_assert((1 << LOG2N) >= E, "transform shorter than the values per thread");
-  fft_stages<T, LOG2N, E, LS, DIR, FULL, 0>(v, lds, tid, tw);
+  fft_stages<T, LOG2N, E, LS, DIR, FULL, PP, 0>(v, lds, lds2, tid, tw);
 }
 
 // ---------------------------------------------------------------------------

@@ -292,20 +292,23 @@ __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ pla
     for (int m = 0; m < ER; ++m) v[m] = S[trv + m * TPR];
     __syncthreads();
     if (nxt.plane >= 0) stage_row<Real, LOG2NX>(planes + (size_t)nxt.plane * psz, nxt.iy, gp, S, trv);
-    // tw: the LDS copy of the nx twiddles of this size (after S)
-    fft_seq<Real, LOG2NX, ER, 1, +1, true>(v, lrow, trv, S + (1 << LOG2NX));
+    // after S: the LDS twiddles (nx/2) and the second exchange row; the two
+    // barriers above separate this transform from the previous one
+    constexpr int nx = 1 << LOG2NX;
+    fft_seq<Real, LOG2NX, ER, 1, +1, true, true>(v, lrow, trv, S + nx, S + nx + nx / 2);
   } else {
     load_row<Real, LOG2NX>(planes + (size_t)p * psz, iy, valid, trv, gp.tlw, gp.tlh, v);
     fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
   }
 }
 
-// LDS copy of the nx twiddles e^{2 pi i k / nx} (slice nx of the table).
+// LDS copy of the twiddles e^{2 pi i k / nx}, k < nx/2 (from slice nx of the
+// table): the radix-8 stages of an nx-point transform read no higher index.
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void load_row_twiddles(cplx<Real>* dst,
                                                   const cplx<Real>* __restrict__ tw) {
   constexpr int nx = 1 << LOG2NX;
-  for (int i = threadIdx.x; i < nx; i += blockDim.x) dst[i] = tw[nx + i];
+  for (int i = threadIdx.x; i < nx / 2; i += blockDim.x) dst[i] = tw[nx + i];
 }
 
 // The nine facet quantities of one row, in the order they become available:

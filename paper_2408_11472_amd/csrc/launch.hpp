@@ -73,14 +73,17 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
 
 // Staging of the next plane row in LDS for the fused row pass (direct
 // global -> LDS loads while the current row transform runs), for single-row
-// blocks whose LDS allows it:
-// after the transform rows, one row of nx elements and the nx twiddles of the
-// row size (read from LDS, so that no global load of the transform has to
-// wait behind the staged row).  The fused kernel keeps room for a full
-// window of partial spectra.
-constexpr size_t kFusedFrontMax = 100 * 1024;
+// blocks whose LDS allows it: after the transform row, one row of nx
+// elements, the first nx/2 twiddles e^{2 pi i k / nx} (the row transform's
+// twiddles are read from LDS, so that no global load of the transform has
+// to wait behind the staged row) and a second transform row (the exchanges
+// alternate between the two, one barrier each).  The fused kernel keeps room
+// for a full window of partial spectra.
+constexpr size_t kFusedFrontMax = 120 * 1024;
 __host__ __device__ constexpr size_t row_stage_bytes(bool stage, int log2nx, int cs) {
-  return stage ? ((size_t)2 * cs << log2nx) : 0;
+  return stage ? ((size_t)cs << log2nx) + ((size_t)cs << (log2nx - 1)) +
+                     lpad_c((size_t)1 << log2nx) * cs
+               : 0;
 }
 __host__ __device__ constexpr bool row_stage_fused(int log2nx, int cs) {
   return row_rpb(log2nx) == 1 &&

@@ -315,4 +315,6 @@ def test_prepared_spectrum_gives_the_same_update(prec, pcode, npdt, nx, ny):
         torch.cuda.synchronize()
         out.append((T.cpu().numpy(), code.cpu().numpy()))
     np.testing.assert_array_equal(out[0][1], out[1][1])
-    assert rel_l2(out[1][0], out[0][0]) <= (1e-13 if prec == "fp64" else 1e-6)
+    # identical scatterers; only the order of the window atomics differs
+    # (cells of up to ~1e3 nearly coherent terms: eps * n_cell)
+    assert rel_l2(out[1][0], out[0][0]) <= (1e-13 if prec == "fp64" else 1e-5)
