@@ -310,7 +310,7 @@ sim_status sim_batch_run(sim_batch *batch, void *const *spec0, void *const *t_fa
  * bench/autotune code sets them per context. */
 #define SIM_TUNE_ROW_BANDS 0      /* blocks of the fused row pass (bands of rows), 0 = default */
 #define SIM_TUNE_ROW_PATH 1       /* row path of sim_update_and_accumulate, one of:             */
-#define SIM_ROW_PATH_AUTO 0       /*   fused row pass where it runs without register spills   */
+#define SIM_ROW_PATH_AUTO 0       /*   the faster on MI355X: currently the split path        */
 #define SIM_ROW_PATH_FUSED 1      /*   fused row pass: facets stay on chip                    */
 #define SIM_ROW_PATH_SPLIT 2      /*   facet row pass into the workspace, then facet accumulate */
 sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);

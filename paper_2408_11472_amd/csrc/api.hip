@@ -304,7 +304,7 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, bo
   RowPlan rpl = row_plan(g->nx, cs);
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, rpl.front_bytes);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
-  rpl.acc_bytes = rpl.front_bytes + (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
+  rpl.acc_bytes = rpl.front_bytes + (size_t)r->n_gates * wk * cs + simk::kWinCtxBytes;
   int target = rpl.threads <= 512 ? kMaxBands : kMaxBands / 2;
   if (c->row_bands > 0 && c->row_bands < target) target = c->row_bands;
   int n_bands, band_rows;
@@ -345,12 +345,16 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
 
 // Row path of the fused call: the fused row pass (facets never leave the
 // chip), or the facet row pass into the workspace followed by the facet
-// accumulate.  Automatic choice: the fused row pass where its kernel keeps
-// the facet fields in registers without spilling (float, rows up to 4096).
+// accumulate.  Automatic choice: the split path.  The fused row kernel holds
+// nine facet fields per value slot in registers (about 250 VGPRs in float,
+// spills in double and for 8192-wide rows), so a CU runs one block of it;
+// the two split kernels keep several blocks per CU and measure faster even
+// with the facet round trip through HBM (4096^2 float: 652 vs 721 us per
+// update; double: 1.28 vs 2.28 ms).
 bool use_split(const sim_ctx* c, const sim_grid* g) {
+  (void)g;
   if (c->row_path == SIM_ROW_PATH_FUSED) return false;
-  if (c->row_path == SIM_ROW_PATH_SPLIT) return true;
-  return c->prec == SIM_PREC_FP64 || g->nx > 4096;
+  return true;
 }
 
 sim_status surface_update_impl(sim_ctx* ctx, const sim_grid* grid, const void* spec0,
@@ -396,7 +400,7 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
   if (band < 1024) band = 1024;
   const int n_bands = (int)((P + band - 1) / band);
   const WinP wp = win_params(c, r, L, wk, n_bands, (int)band);
-  const size_t lds = (size_t)r->n_gates * wk * cs + 72 * sizeof(int);
+  const size_t lds = (size_t)r->n_gates * wk * cs + simk::kWinCtxBytes;
   void* const fp[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
                        f->dh};
   void* Tj = (char*)t_fast + (size_t)j * r->n_gates * r->n_doppler * cs;

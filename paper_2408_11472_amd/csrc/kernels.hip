@@ -450,7 +450,7 @@ __device__ __forceinline__ WinCtx<Real> win_ctx(unsigned char* smem, size_t fft_
   w.win = reinterpret_cast<cplx<Real>*>(smem + fft_bytes);
   int* ints = reinterpret_cast<int*>(smem + fft_bytes + (size_t)rp.G * wp.WK * sizeof(cplx<Real>));
   w.st = ints;
-  w.red = ints + 8;
+  w.red = ints + kWinStateInts;
   w.Tj = Tj;
   w.band = band;
   return w;
@@ -548,7 +548,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
 constexpr int EA = 4;
 
 template <typename Real>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(acc_threads(sizeof(cplx<Real>)))
 accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
                          cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1028,7 +1028,8 @@ hipError_t launch_accumulate_facets(void* const* fac, const GridP& gp, const Rad
                                     hipStream_t st) {
   FacetPtrs<Real> fp;
   for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)fac[i];
-  hipLaunchKernelGGL(accumulate_facets_kernel<Real>, dim3(wp.n_bands), dim3(256), lds_bytes, st,
+  hipLaunchKernelGGL(accumulate_facets_kernel<Real>, dim3(wp.n_bands),
+                     dim3(acc_threads(sizeof(cplx<Real>))), lds_bytes, st,
                      fp, gp, rp, wp, (cplx<Real>*)Tj, code);
   return hipGetLastError();
 }

@@ -101,7 +101,7 @@ template <typename Real>
 struct WinCtx {
   cplx<Real>* win;   // LDS [G][WK]
   int* st;           // LDS state[8]
-  int* red;          // LDS scratch[64]
+  int* red;          // LDS scratch[kWinRedInts]
   cplx<Real>* Tj;    // T_fast[j] (overflow path only)
   int band;
 };
