@@ -40,7 +40,9 @@ namespace {
 using simk::kLdsBudget;
 constexpr size_t kWindowBudget = 32 * 1024;    // LDS of one window of partial spectra
 constexpr int kSlots = 4;                      // window slots per band
-constexpr int kMaxBands = 512;
+constexpr int kMaxBands = 512;       // bands (blocks) of the fused row pass
+constexpr int kAccBands = 512;       // bands (blocks) of the facet accumulate
+constexpr int kWsBands = kAccBands > kMaxBands ? kAccBands : kMaxBands;
 
 bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(long v) {
@@ -132,11 +134,11 @@ WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
   L.planes = off;
   off = align256(off + 6 * P * cs);
   L.part = off;
-  off = align256(off + (size_t)kMaxBands * kSlots * r->n_gates * (size_t)(wk > 0 ? wk : 1) * cs);
+  off = align256(off + (size_t)kWsBands * kSlots * r->n_gates * (size_t)(wk > 0 ? wk : 1) * cs);
   L.hdr = off;
-  off = align256(off + (size_t)kMaxBands * kSlots * 16);
+  off = align256(off + (size_t)kWsBands * kSlots * 16);
   L.bandcnt = off;
-  off = align256(off + (size_t)kMaxBands * 8 * 4);
+  off = align256(off + (size_t)kWsBands * 8 * 4);
   // facet fields of the split row path (9 planes of P reals)
   L.facets = off;
   L.facet_stride = align256(P * (cs / 2));
@@ -396,7 +398,7 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
   const size_t P = (size_t)g->nx * g->ny;
-  size_t band = P / kMaxBands;
+  size_t band = P / kAccBands;
   if (band < 1024) band = 1024;
   const int n_bands = (int)((P + band - 1) / band);
   const WinP wp = win_params(c, r, L, wk, n_bands, (int)band);
