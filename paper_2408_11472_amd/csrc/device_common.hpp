@@ -256,58 +256,73 @@ __device__ __forceinline__ void fft_seq(cplx<T>* v, cplx<T>* lds, int tid,
 
 // ---------------------------------------------------------------------------
 // Block reductions (blockDim.x a multiple of 64, at most 1024 threads).
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+// Within a wave the lanes are combined with DPP moves (quad swaps, half-row
+// and row mirrors: each row of 16 lanes then holds its reduction) and the
+// four rows are read with readlane, so no LDS instruction is issued.
+template <typename T, typename Op>
+__device__ __forceinline__ T row16_reduce(T v, Op op) {
+  v = op(v, (T)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = op(v, (T)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = op(v, (T)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = op(v, (T)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false));  // row_mirror
   return v;
 }
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  v = row16_reduce(v, op);
+  const T a = (T)__builtin_amdgcn_readlane((int)v, 0), b = (T)__builtin_amdgcn_readlane((int)v, 16);
+  const T c = (T)__builtin_amdgcn_readlane((int)v, 32), d = (T)__builtin_amdgcn_readlane((int)v, 48);
+  return op(op(a, b), op(c, d));
 }
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+struct OpMin { __device__ int operator()(int a, int b) const { return min(a, b); } };
+struct OpMax { __device__ int operator()(int a, int b) const { return max(a, b); } };
+struct OpAdd { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
+
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce(v, OpMin()); }
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce(v, OpMax()); }
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_reduce(v, OpAdd()); }
 
 // Reduce four ints (two mins, two maxes) over the block; scratch holds
-// 4 * 16 ints.  Result broadcast to every thread.
+// 4 * 16 ints.  Result broadcast to every thread: lane l of each wave reads
+// wave l's partials and the first 16 lanes are reduced with DPP.
 __device__ __forceinline__ void block_minmax2(int& amin, int& amax, int& bmin, int& bmax,
                                               int* scratch) {
   amin = wave_min(amin);
   amax = wave_max(amax);
   bmin = wave_min(bmin);
   bmax = wave_max(bmax);
-  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
     scratch[wv] = amin;
     scratch[16 + wv] = amax;
     scratch[32 + wv] = bmin;
     scratch[48 + wv] = bmax;
   }
   __syncthreads();
-  amin = scratch[0];
-  amax = scratch[16];
-  bmin = scratch[32];
-  bmax = scratch[48];
-  for (int w = 1; w < nw; ++w) {
-    amin = min(amin, scratch[w]);
-    amax = max(amax, scratch[16 + w]);
-    bmin = min(bmin, scratch[32 + w]);
-    bmax = max(bmax, scratch[48 + w]);
-  }
+  const bool in = lane < nw;
+  int p0 = in ? scratch[lane] : 0x7fffffff;
+  int p1 = in ? scratch[16 + lane] : -0x7fffffff - 1;
+  int p2 = in ? scratch[32 + lane] : 0x7fffffff;
+  int p3 = in ? scratch[48 + lane] : -0x7fffffff - 1;
+  p0 = row16_reduce(p0, OpMin());
+  p1 = row16_reduce(p1, OpMax());
+  p2 = row16_reduce(p2, OpMin());
+  p3 = row16_reduce(p3, OpMax());
+  amin = __builtin_amdgcn_readlane(p0, 0);
+  amax = __builtin_amdgcn_readlane(p1, 0);
+  bmin = __builtin_amdgcn_readlane(p2, 0);
+  bmax = __builtin_amdgcn_readlane(p3, 0);
   __syncthreads();
 }
 
 __device__ __forceinline__ int block_max(int a, int* scratch) {
   a = wave_max(a);
-  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) scratch[wv] = a;
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) scratch[wv] = a;
   __syncthreads();
-  a = scratch[0];
-  for (int w = 1; w < nw; ++w) a = max(a, scratch[w]);
+  int p = lane < nw ? scratch[lane] : -0x7fffffff - 1;
+  p = row16_reduce(p, OpMax());
+  a = __builtin_amdgcn_readlane(p, 0);
   __syncthreads();
   return a;
 }
