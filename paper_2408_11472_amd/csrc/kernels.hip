@@ -276,12 +276,15 @@ struct NextRow {
 // recomputed per transform instead of being kept live across all six.
 // Staged mode: the row was loaded into S ahead of time; once every thread
 // has its values, the next transform's row is put in flight into S.
+// Unstaged mode with lrow2 set: the exchanges alternate between lrow and
+// lrow2 (one barrier each), and a barrier after the row loads separates this
+// transform from the previous one.
 template <typename Real, int LOG2NX, bool STAGE>
 __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ planes, size_t psz,
                                               int p, int iy, bool valid, int tr,
                                               const GridP& gp, cplx<Real>* lrow, cplx<Real>* S,
                                               NextRow nxt, const cplx<Real>* __restrict__ tw,
-                                              cplx<Real>* v) {
+                                              cplx<Real>* v, cplx<Real>* lrow2 = nullptr) {
   int trv = tr;
   asm volatile("" : "+v"(trv));
   if constexpr (STAGE) {
@@ -298,7 +301,12 @@ __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ pla
     fft_seq<Real, LOG2NX, ER, 1, +1, true, true>(v, lrow, trv, S + nx, S + nx + nx / 2);
   } else {
     load_row<Real, LOG2NX>(planes + (size_t)p * psz, iy, valid, trv, gp.tlw, gp.tlh, v);
-    fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
+    if (lrow2) {
+      __syncthreads();
+      fft_seq<Real, LOG2NX, ER, 1, +1, false, true>(v, lrow, trv, tw, lrow2);
+    } else {
+      fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
+    }
   }
 }
 
@@ -324,25 +332,25 @@ __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes
                                            int iy, bool valid, int tr, const GridP& gp,
                                            cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F) {
+                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr) {
   cplx<Real> v[ER];
   Real hx[ER], hy[ER], dxx[ER];
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
-                                     NextRow{2, iy_stage}, tw, v);  // Dy + i h_x
+                                     NextRow{2, iy_stage}, tw, v, lrow2);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
-                                     NextRow{3, iy_stage}, tw, v);  // h_y + i Dx_x
+                                     NextRow{3, iy_stage}, tw, v, lrow2);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     hy[m] = v[m].x;
     dxx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
-                                     NextRow{0, iy_stage}, tw, v);  // Dx_y + i Dy_y
+                                     NextRow{0, iy_stage}, tw, v, lrow2);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     const Real dxy = v[m].x, dyy = v[m].y;
@@ -362,17 +370,17 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
                                            int iy, bool valid, int tr, const GridP& gp,
                                            cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            int iy_next, const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F) {
+                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr) {
   cplx<Real> v[ER];
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
-                                     NextRow{4, iy_stage}, tw, v);  // h + i Dx
+                                     NextRow{4, iy_stage}, tw, v, lrow2);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
-                                     NextRow{5, iy_stage}, tw, v);  // dh + i dDx
+                                     NextRow{5, iy_stage}, tw, v, lrow2);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.dh[m] = v[m].x;
@@ -380,7 +388,7 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
   }
   // the row after this one starts with plane 1 (iy_next < 0: none)
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
-                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v);  // dDy
+                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v, lrow2);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
 }
@@ -401,6 +409,10 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   const int rl = threadIdx.x / TPR, tr = threadIdx.x % TPR;
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
   cplx<Real>* S = nullptr;   // (no staging row)
+  // second exchange buffer of this row (ping-pong exchanges), where it fits
+  cplx<Real>* lrow2 = row_facets_pp(LOG2NX, sizeof(cplx<Real>))
+                          ? reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)(RPB + rl) * lpad(nx)
+                          : nullptr;
   const size_t psz = (size_t)nx * ny;
   // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
   // contiguous run of row chunks, so that the chunks sharing a plane tile
@@ -414,7 +426,7 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
     const bool valid = iy < ny;
     const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB : -1;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F);
+    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, lrow2);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -426,7 +438,7 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
       }
     }
     row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
-                                    F);
+                                    F, lrow2);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -979,7 +991,7 @@ static hipError_t rowpass_facets_t(const void* planes, const GridP& gp, const Fa
   const int blocks = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
   constexpr int cs = sizeof(cplx<Real>);
   hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks), dim3(row_threads(L)),
-                     row_fft_lds(L, cs), st,
+                     row_facets_lds(L, cs), st,
                      (const cplx<Real>*)planes,
                      with_tiles<Real>(gp), fp, (const cplx<Real>*)tw);
   return hipGetLastError();

@@ -80,6 +80,14 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
 // alternate between the two, one barrier each).  The fused kernel keeps room
 // for a full window of partial spectra.
 constexpr size_t kFusedFrontMax = 120 * 1024;
+// The facet row pass alternates its exchanges between two transform rows
+// where both fit the LDS budget.
+__host__ __device__ constexpr bool row_facets_pp(int log2nx, int cs) {
+  return 2 * row_fft_lds(log2nx, cs) <= kLdsBudget;
+}
+__host__ __device__ constexpr size_t row_facets_lds(int log2nx, int cs) {
+  return (row_facets_pp(log2nx, cs) ? 2 : 1) * row_fft_lds(log2nx, cs);
+}
 __host__ __device__ constexpr size_t row_stage_bytes(bool stage, int log2nx, int cs) {
   return stage ? ((size_t)cs << log2nx) + ((size_t)cs << (log2nx - 1)) +
                      lpad_c((size_t)1 << log2nx) * cs
