@@ -39,15 +39,15 @@ ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48,
 # copy, and VALU wave-instructions per launch (SQ_INSTS_VALU).
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "e6c3610329988b80",
-    "fp32": {"traffic_bytes": {"surface_colpass": 1293e6, "surface_rowpass": 1410e6,
+    "source_sha": "d08d5daab262b17a",
+    "fp32": {"traffic_bytes": {"surface_colpass": 1290e6, "surface_rowpass": 1410e6,
                                "accumulate_facets": 606e6},
-             "valu_wave_instr": {"surface_colpass": 1.85e8, "surface_rowpass": 1.00e8,
-                                 "accumulate_facets": 8.43e7}},
+             "valu_wave_instr": {"surface_colpass": 1.85e+08, "surface_rowpass": 1.01e+08,
+                                 "accumulate_facets": 8.43e+07}},
     "fp64": {"traffic_bytes": {"surface_colpass": 2151e6, "surface_rowpass": 2824e6,
                                "accumulate_facets": 1210e6},
-             "valu_wave_instr": {"surface_colpass": 1.96e8, "surface_rowpass": 9.63e7,
-                                 "accumulate_facets": 9.82e7}},
+             "valu_wave_instr": {"surface_colpass": 1.96e+08, "surface_rowpass": 1.03e+08,
+                                 "accumulate_facets": 1.01e+08}},
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
 
