@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/simradar.h"
@@ -828,12 +829,23 @@ sim_status sim_profile_read(sim_ctx* ctx, sim_kernel_times* out) {
 
 }  // extern "C"
 
+// Members run on up to kBatchLanes streams ("lanes") at once, each lane with
+// its own slice of the workspace, so that the launches of small grids, which
+// do not fill the GPU, overlap with the others.  Members are dealt to lanes
+// largest first, each to the lane with the least work so far.
+constexpr int kBatchLanes = 4;
+
 struct sim_batch {
   sim_ctx* ctx;
   std::vector<sim_grid> grids;
   std::vector<sim_radar> radars;
   std::vector<int32_t> updates;
   std::vector<size_t> prep_off;   // prepared spectrum of each member in the workspace
+  std::vector<int> lane_of;       // lane of each member
+  std::vector<size_t> lane_off, lane_bytes;   // workspace slice of each lane
+  std::vector<hipStream_t> lane_st;
+  std::vector<hipEvent_t> lane_ev;            // join events
+  hipEvent_t fork_ev;
   size_t ws_bytes;
   // captured graph and the pointers it was captured with
   hipGraphExec_t exec;
@@ -864,26 +876,46 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
                                               (char*)c->ws + b->prep_off[r], st);
     if (s != SIM_OK) return s;
   }
-  for (int j = 0; j <= jmax; ++j) {
-    for (int r = 0; r < R; ++r) {
-      if (j > b->updates[r]) continue;
-      const sim_radar& rr = b->radars[r];
-      const double t = ((double)j * rr.n_fast) / rr.prf_hz;
-      const sim_status s = sim_update_and_accumulate_prepared(
-          c, &b->grids[r], (char*)c->ws + b->prep_off[r], &rr, t, j, t_fast[r],
-          b->updates[r] + 1, nullptr, nullptr, st);
-      if (s != SIM_OK) return s;
+  // fork the lanes off the caller's stream (also under graph capture), run
+  // each lane's members update-major on its stream with its workspace slice,
+  // and join them back
+  const int NL = (int)b->lane_st.size();
+  sim_status s = dev(hipEventRecord(b->fork_ev, st));
+  if (s != SIM_OK) return s;
+  for (int l = 0; l < NL; ++l) {
+    s = dev(hipStreamWaitEvent(b->lane_st[l], b->fork_ev, 0));
+    if (s != SIM_OK) return s;
+  }
+  sim_status first = SIM_OK;
+  for (int l = 0; l < NL && first == SIM_OK; ++l) {
+    sim_ctx lc = *c;            // same device and twiddles, the lane's workspace
+    lc.ws = (char*)c->ws + b->lane_off[l];
+    lc.ws_bytes = b->lane_bytes[l];
+    lc.profiling = false;
+    hipStream_t ls = b->lane_st[l];
+    for (int j = 0; j <= jmax && first == SIM_OK; ++j) {
+      for (int r = 0; r < R; ++r) {
+        if (b->lane_of[r] != l || j > b->updates[r]) continue;
+        const sim_radar& rr = b->radars[r];
+        const double t = ((double)j * rr.n_fast) / rr.prf_hz;
+        first = sim_update_and_accumulate_prepared(
+            &lc, &b->grids[r], (char*)c->ws + b->prep_off[r], &rr, t, j, t_fast[r],
+            b->updates[r] + 1, nullptr, nullptr, ls);
+        if (first != SIM_OK) break;
+      }
+    }
+    for (int r = 0; r < R && first == SIM_OK && y; ++r) {
+      if (b->lane_of[r] != l || !y[r]) continue;
+      first = sim_segments_to_iq(&lc, &b->radars[r], t_fast[r], b->updates[r] + 1, y[r], ls);
     }
   }
-  if (y) {
-    for (int r = 0; r < R; ++r) {
-      if (!y[r]) continue;
-      const sim_status s = sim_segments_to_iq(c, &b->radars[r], t_fast[r], b->updates[r] + 1,
-                                              y[r], st);
-      if (s != SIM_OK) return s;
-    }
+  // always join, so that a capture stays well formed
+  for (int l = 0; l < NL; ++l) {
+    s = dev(hipEventRecord(b->lane_ev[l], b->lane_st[l]));
+    if (s == SIM_OK) s = dev(hipStreamWaitEvent(st, b->lane_ev[l], 0));
+    if (s != SIM_OK && first == SIM_OK) first = s;
   }
-  return SIM_OK;
+  return first;
 }
 
 }  // namespace
@@ -908,21 +940,64 @@ sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
     const size_t need = ws_layout(&grids[r], &radars[r], csize(ctx)).total;
     ws = need > ws ? need : ws;
   }
+  (void)ws;
+  sim_status su = use_device(ctx);
+  if (su != SIM_OK) return su;
   sim_batch* b = new (std::nothrow) sim_batch;
   if (!b) return SIM_ERR_DEVICE;
   b->ctx = ctx;
   b->grids.assign(grids, grids + n_real);
   b->radars.assign(radars, radars + n_real);
   b->updates.assign(n_updates, n_updates + n_real);
-  // members share the largest per-call layout; their prepared spectra follow
-  ws = align256(ws);
+  // lanes: members largest first, each to the least loaded lane
+  const int NL = n_real < kBatchLanes ? n_real : kBatchLanes;
+  std::vector<double> load(NL, 0.0);
+  std::vector<int> order(n_real);
+  for (int r = 0; r < n_real; ++r) order[r] = r;
+  auto work = [&](int r) {
+    return (double)grids[r].nx * grids[r].ny * (double)(n_updates[r] + 1);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  b->lane_of.assign(n_real, 0);
+  b->lane_bytes.assign(NL, 0);
+  for (int r : order) {
+    int best = 0;
+    for (int l = 1; l < NL; ++l)
+      if (load[l] < load[best]) best = l;
+    b->lane_of[r] = best;
+    load[best] += work(r);
+    const size_t need = ws_layout(&grids[r], &radars[r], csize(ctx)).total;
+    if (need > b->lane_bytes[best]) b->lane_bytes[best] = need;
+  }
+  // workspace: the lanes' slices, then every member's prepared spectrum
+  size_t off = 0;
+  for (int l = 0; l < NL; ++l) {
+    b->lane_off.push_back(off);
+    off = align256(off + b->lane_bytes[l]);
+  }
   for (int r = 0; r < n_real; ++r) {
     size_t pb = 0;
     (void)sim_prepared_spectrum_size(ctx, &grids[r], &pb);
-    b->prep_off.push_back(ws);
-    ws = align256(ws + pb);
+    b->prep_off.push_back(off);
+    off = align256(off + pb);
   }
-  b->ws_bytes = ws;
+  b->ws_bytes = off;
+  bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int l = 0; l < NL && ok; ++l) {
+    hipStream_t ls;
+    hipEvent_t le;
+    ok = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) break;
+    b->lane_st.push_back(ls);
+    ok = hipEventCreateWithFlags(&le, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->lane_ev.push_back(le);
+  }
+  if (!ok) {
+    for (hipStream_t ls : b->lane_st) (void)hipStreamDestroy(ls);
+    for (hipEvent_t le : b->lane_ev) (void)hipEventDestroy(le);
+    delete b;
+    return SIM_ERR_DEVICE;
+  }
   b->have_graph = false;
   b->graph_stream = nullptr;
   *batch = b;
@@ -932,7 +1007,13 @@ sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
 sim_status sim_batch_destroy(sim_batch* b) {
   if (!b) return SIM_OK;
   sim_status s = SIM_OK;
+  if (use_device(b->ctx) != SIM_OK) s = SIM_ERR_DEVICE;
   if (b->have_graph && hipGraphExecDestroy(b->exec) != hipSuccess) s = SIM_ERR_DEVICE;
+  for (hipStream_t ls : b->lane_st)
+    if (hipStreamDestroy(ls) != hipSuccess) s = SIM_ERR_DEVICE;
+  for (hipEvent_t le : b->lane_ev)
+    if (hipEventDestroy(le) != hipSuccess) s = SIM_ERR_DEVICE;
+  if (hipEventDestroy(b->fork_ev) != hipSuccess) s = SIM_ERR_DEVICE;
   delete b;
   return s;
 }
