@@ -206,10 +206,12 @@ sim_status sim_update_and_accumulate(sim_ctx *ctx, const sim_grid *grid,
                                      int32_t *facet_code, void *stream);
 
 /* The spectrum in the layout the surface transform's first (column) pass
- * reads: for each strip of adjacent columns it works on, rows in order, the
- * pair (c(k), c(-k)) of every column of the strip, so that each update reads
- * it contiguously.  Same content as the FFT-order spectrum (Sec. II.A: the
- * surface is synthesised from it at every update); made once per run.
+ * reads: the pass works on the columns kx >= 0 only (the surface fields are
+ * real), and for each strip of adjacent columns it works on, rows in order,
+ * the buffer holds the pair (c(k), c(-k)) of every column of the strip, so
+ * that each update reads it contiguously.  Same content as the FFT-order
+ * spectrum (Sec. II.A: the surface is synthesised from it at every update);
+ * made once per run.
  *   spec0     [ny][nx] complex, FFT order, read only.
  *   prepared  caller-owned device buffer of sim_prepared_spectrum_size bytes,
  *             16-byte aligned, written; its layout depends on grid and
@@ -320,7 +322,7 @@ sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
  * events recorded on the stream it is launched on; sim_profile_read waits
  * for the last event and returns, per kernel kind, the summed duration and
  * the launch count since the profile was (re)enabled. */
-#define SIM_KERNEL_SURFACE_COLPASS 0      /* spectrum -> 6 planes, FFT along y   */
+#define SIM_KERNEL_SURFACE_COLPASS 0      /* spectrum -> 8 half planes, FFT in y */
 #define SIM_KERNEL_SURFACE_ROWPASS 1      /* FFT along x -> facet SoA            */
 #define SIM_KERNEL_FUSED_ROWPASS 2        /* FFT along x + scatterers + windows  */
 #define SIM_KERNEL_ACCUMULATE_FACETS 3    /* facet SoA -> scatterers + windows   */

@@ -127,13 +127,18 @@ struct WsLayout {
   size_t planes, part, hdr, bandcnt, facets, facet_stride, total;
 };
 
+// Bytes of the column pass's half planes.
+size_t plane_bytes(const sim_grid* g, size_t cs) {
+  return simk::kHalfPlanes * simk::half_plane_elems(ilog2(g->nx), ilog2(g->ny), (int)cs) * cs;
+}
+
 WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
   WsLayout L;
   const size_t P = (size_t)g->nx * g->ny;
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
   size_t off = 0;
   L.planes = off;
-  off = align256(off + 6 * P * cs);
+  off = align256(off + plane_bytes(g, cs));
   L.part = off;
   off = align256(off + (size_t)kWsBands * kSlots * r->n_gates * (size_t)(wk > 0 ? wk : 1) * cs);
   L.hdr = off;
@@ -255,7 +260,7 @@ sim_status common_checks(sim_ctx* c, const sim_grid* g, const sim_radar* r, WsLa
     *L = ws_layout(g, r, csize(c));
     if (L->total > c->ws_bytes) return SIM_ERR_WORKSPACE;
   } else {
-    const size_t need = align256(6 * (size_t)g->nx * g->ny * csize(c));
+    const size_t need = align256(plane_bytes(g, csize(c)));
     if (need > c->ws_bytes) return SIM_ERR_WORKSPACE;
     L->planes = 0;
   }
@@ -604,7 +609,9 @@ sim_status sim_prepared_spectrum_size(const sim_ctx* ctx, const sim_grid* grid, 
   if (!ctx || !bytes) return SIM_ERR_ARG;
   const sim_status s = check_grid(ctx, grid);
   if (s != SIM_OK) return s;
-  *bytes = 2 * (size_t)grid->nx * grid->ny * csize(ctx);
+  // the pair (c(k), c(-k)) of every mode kx >= 0 (half width of the planes)
+  const size_t cs = csize(ctx);
+  *bytes = 2 * simk::half_plane_elems(ilog2(grid->nx), ilog2(grid->ny), (int)cs) * cs;
   return SIM_OK;
 }
 

@@ -334,6 +334,7 @@ struct GridP {
   int nx, ny, log2nx, log2ny;
   int cwm;
   int tlw, tlh;   // log2 of the plane tile width and height (set at launch)
+  int lhw;        // log2 of the half-plane width (set at launch)
   double dx, dy, x_origin, y_origin, gravity, sqrt_g;
 };
 

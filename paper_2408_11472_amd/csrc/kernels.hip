@@ -1,9 +1,10 @@
 // HIP kernels of the fast-mode hot path for gfx950, with their host launch
 // wrappers (called by the C ABI in api.cpp).
 //
-//   colpass              spectrum evolution + Hermitian packing of the 11 real
-//                        surface fields into 6 complex spectra, inverse FFT
-//                        along y (Sec. II.A surface synthesis, first half)
+//   colpass              spectrum evolution of the half spectrum kx >= 0,
+//                        one spectrum per y-dependence of the 11 real surface
+//                        fields, inverse FFT along y (Sec. II.A surface
+//                        synthesis, first half)
 //   rowpass_facets       inverse FFT along x, facet geometry, facet SoA out
 //   rowpass_accumulate   inverse FFT along x, facet geometry, scatterers and
 //                        rasterisation into LDS windows (Algorithm 1), fused
@@ -22,12 +23,19 @@ namespace simk {
 //
 // With zeta(k, t) = 1/2 [c(k) e^{-i w t} + conj(c(-k)) e^{+i w t}] (Hermitian
 // in k) and its increment dzeta over dt, every real field F with multiplier
-// M_F has spectrum M_F zeta, and two real fields F1, F2 are carried by one
-// complex transform of M_F1 zeta + i M_F2 zeta.  Plane layout:
-//   0: h  + i Dx      1: Dy + i h_x     2: h_y + i Dx_x
-//   3: Dx_y + i Dy_y  4: dh + i dDx     5: dDy
-// Each column strip is handled by two blocks: group 0 makes planes 0-3 from
-// zeta, group 1 planes 4-5 from dzeta, so a thread keeps one spectral state.
+// M_F has spectrum M_F zeta.  Along a column kx is fixed, so fields whose
+// multipliers differ by a factor of kx alone share one column transform
+// (h and h_x = i kx h, ...), and the factor is applied by the row pass.
+// Every field is real, so its column transform at -kx is the conjugate of
+// the one at kx: only the columns kx >= 0 are transformed.  Half planes
+// (multiplier of the column transform; fields the row pass takes from it):
+//   0: 1            h, h_x          4: -ky^2/|k|      Dy_y
+//   1: 1/|k|        Dx, Dx_x        5: 1 (of dzeta)   dh
+//   2: i ky/|k|     Dy, Dx_y        6: 1/|k| (dzeta)  dDx
+//   3: i ky         h_y             7: i ky/|k| (dz.) dDy
+// (the CWM planes 1, 2, 4, 6, 7 are zero without the CWM).  Each column
+// strip is handled by two blocks: group 0 makes planes 0-4 from zeta, group
+// 1 planes 5-7 from dzeta, so a thread keeps one spectral state.
 // PREP: spec is the prepared spectrum (prepare_spectrum_kernel): per column
 // strip, rows in order, the pair (c(k), c(-k)) of each column of the strip,
 // so the loads of a wave are one contiguous run instead of CPB-element
@@ -52,13 +60,13 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
   const int item = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
                                    : blockIdx.x;
   const int strip = item >> 1, group = item & 1;
-  const int ix = strip * CPB + c;
+  const int ix = strip * CPB + c;          // kx index, 0 <= ix < half width
+  const bool live = ix < nx / 2;           // the Nyquist column carries no wave
   const int mx = (nx - ix) & (nx - 1);
   const double twopi = 6.283185307179586476925;
   const double dkx = twopi / ((double)nx * gp.dx);
   const double dky = twopi / ((double)ny * gp.dy);
-  const int nxs = ix < nx / 2 ? ix : ix - nx;
-  const double kx = dkx * (double)nxs;
+  const double kx = dkx * (double)ix;
   const Real dcw = gp.cwm ? (Real)1 : (Real)0;
 
   cplx<Real> st[E];
@@ -67,7 +75,7 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
     const int iy = s + m * TPS;
     const int my = (ny - iy) & (ny - 1);
     const int nys = iy < ny / 2 ? iy : iy - ny;
-    const bool skip = (ix == nx / 2) || (iy == ny / 2) || (ix == 0 && iy == 0);
+    const bool skip = !live || (iy == ny / 2) || (ix == 0 && iy == 0);
     cplx<Real> z = mk<Real>(0, 0);
     if (!skip) {
       cplx<Real> h0, hm;
@@ -127,16 +135,20 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
     __builtin_amdgcn_sched_barrier(0);
   }
 
-  const int f0 = group == 0 ? 0 : 4;
-  const int f1 = group == 0 ? 4 : 6;
+  const int f0 = group == 0 ? 0 : 5;
+  const int f1 = group == 0 ? 5 : 8;
+  const int lhw = gp.lhw;
+  const size_t psz = (size_t)ny << lhw;
 #pragma unroll 1
   for (int f = f0; f < f1; ++f) {
     // Opaque copies of the thread coordinates: everything derived from them
-    // (store addresses, wavenumbers, LDS offsets) is recomputed per field
+    // (store addresses, wavenumbers, LDS offsets) is recomputed per plane
     // instead of being hoisted out of the loop and kept in registers.
     int sv = s, ixv = ix;
     asm volatile("" : "+v"(sv), "+v"(ixv));
-    const Real kxv = (Real)dkx * (Real)(ixv < nx / 2 ? ixv : ixv - nx);
+    const Real kxv = (Real)dkx * (Real)ixv;
+    // multiplier r (real planes) or i r (imaginary planes)
+    const bool imag = f == 2 || f == 3 || f == 7;
     cplx<Real> v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -145,57 +157,62 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       const Real ky = (Real)dky * (Real)nys;
       const Real k2 = kxv * kxv + ky * ky;
       const Real ik = k2 > (Real)0 ? rsqrt(k2) : (Real)0;
-      cplx<Real> mul;
+      Real r;
       switch (f) {
         case 0:
-        case 4: mul = mk<Real>((Real)1 - dcw * kxv * ik, (Real)0); break;
-        case 1: mul = mk<Real>(-kxv, dcw * ky * ik); break;
-        case 2: mul = mk<Real>((Real)0, ky - dcw * kxv * kxv * ik); break;
-        case 3: mul = mk<Real>(-dcw * kxv * ky * ik, -dcw * ky * ky * ik); break;
-        default: mul = mk<Real>((Real)0, dcw * ky * ik); break;
+        case 5: r = (Real)1; break;
+        case 1:
+        case 6: r = dcw * ik; break;
+        case 3: r = ky; break;
+        case 4: r = -dcw * ky * ky * ik; break;
+        default: r = dcw * ky * ik; break;   // 2, 7
       }
-      v[m] = cmul(st[m], mul);
+      const cplx<Real> z = st[m];
+      v[m] = imag ? mk<Real>(-r * z.y, r * z.x) : mk<Real>(r * z.x, r * z.y);
     }
     fft_seq<Real, LOG2NY, E, CPB, +1>(v, lds + (ixv - strip * CPB), sv, tw);
     // tiled plane layout (TW = CPB columns by TH rows per tile)
     constexpr int LW = tile_lw(LOG2NY, sizeof(cplx<Real>));
     constexpr int LH = tile_lh(LOG2NY, sizeof(cplx<Real>));
-    cplx<Real>* out = planes + (size_t)f * nx * ny;
+    cplx<Real>* out = planes + (size_t)f * psz;
     const int cw = ixv & ((1 << LW) - 1), tx = ixv >> LW;
     if constexpr (TPS % (1 << LH) == 0) {
       // rows s + m TPS: the tile row advances by TPS / TH per slot
-      out += (((size_t)(sv >> LH) * (size_t)(nx >> LW) + tx) << (LW + LH)) +
+      out += ((((size_t)(sv >> LH) << (lhw - LW)) + tx) << (LW + LH)) +
              ((sv & ((1 << LH) - 1)) << LW) + cw;
 #pragma unroll
-      for (int m = 0; m < E; ++m) out[(size_t)m * TPS * nx] = v[m];
+      for (int m = 0; m < E; ++m) out[(size_t)m * TPS << lhw] = v[m];
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int iy = sv + m * TPS;
-        out[(((size_t)(iy >> LH) * (size_t)(nx >> LW) + tx) << (LW + LH)) +
+        out[((((size_t)(iy >> LH) << (lhw - LW)) + tx) << (LW + LH)) +
             ((iy & ((1 << LH) - 1)) << LW) + cw] = v[m];
       }
     }
   }
 }
 
-// The prepared spectrum of the column pass: element (iy, ix) of the
-// FFT-order spectrum and its mirror (-iy, -ix) side by side, at position
-// (strip ny + iy) CPB + c for ix = strip CPB + c.  One thread per element,
-// rows read in order.
+// The prepared spectrum of the column pass: for each column ix of the half
+// width (kx >= 0) and row iy, the FFT-order spectrum's element (iy, ix) and
+// its mirror (-iy, -ix) side by side, at position (strip ny + iy) CPB + c
+// for ix = strip CPB + c; zeros for the columns from nx/2 on.  One thread per
+// element, rows read in order.
 template <typename Real>
 __global__ void __launch_bounds__(256)
 prepare_spectrum_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ out, int nx,
-                        int ny, int cpb) {
-  const size_t n = (size_t)nx * ny;
+                        int ny, int lhw, int cpb) {
+  const size_t n = (size_t)ny << lhw;
+  const int hw = 1 << lhw;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
-    const int iy = (int)(i / nx), ix = (int)(i % nx);
+    const int iy = (int)(i >> lhw), ix = (int)(i & (size_t)(hw - 1));
     const int my = (ny - iy) & (ny - 1), mx = (nx - ix) & (nx - 1);
     const int strip = ix / cpb, c = ix % cpb;
     cplx<Real>* o = out + 2 * (((size_t)strip * ny + iy) * cpb + c);
-    o[0] = spec[i];
-    o[1] = spec[(size_t)my * nx + mx];
+    const bool live = ix < nx / 2;
+    o[0] = live ? spec[(size_t)iy * nx + ix] : mk<Real>(0, 0);
+    o[1] = live ? spec[(size_t)my * nx + mx] : mk<Real>(0, 0);
   }
 }
 
@@ -205,48 +222,196 @@ prepare_spectrum_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restr
 
 constexpr int ER = kRowE;
 
-// Elements tr + m TPR of row iy of a plane in the tiled layout (tiles of
-// 2^lw columns by 2^lh rows).
+// The six row transforms.  Transform q inverts A + i B along x (two real
+// fields in one complex transform), A and B taken from half planes a and b
+// times a factor of kx: 1, i kx or (i kx)^2 = -kx^2.  Transform 5 carries
+// one field (b < 0).
+constexpr int kFac1 = 0, kFacIKx = 1, kFacKx2 = 2;
+struct PairSrc {
+  int a, fa, b, fb;
+};
+__host__ __device__ constexpr PairSrc pair_src(int q) {
+  return q == 0   ? PairSrc{0, kFac1, 1, kFacIKx}     // h + i Dx
+         : q == 1 ? PairSrc{2, kFac1, 0, kFacIKx}     // Dy + i h_x
+         : q == 2 ? PairSrc{3, kFac1, 1, kFacKx2}     // h_y + i Dx_x
+         : q == 3 ? PairSrc{2, kFacIKx, 4, kFac1}     // Dx_y + i Dy_y
+         : q == 4 ? PairSrc{5, kFac1, 6, kFacIKx}     // dh + i dDx
+                  : PairSrc{7, kFac1, -1, kFac1};     // dDy
+}
+
+template <typename Real>
+__device__ __forceinline__ cplx<Real> kx_factor(cplx<Real> z, int fac, Real kx) {
+  if (fac == kFacIKx) return mk<Real>(-kx * z.y, kx * z.x);
+  if (fac == kFacKx2) {
+    const Real f = -kx * kx;
+    return mk<Real>(f * z.x, f * z.y);
+  }
+  return z;
+}
+
+// Input of transform q at column i from the half-plane values a, b of
+// column idx: idx = i for i < nx/2, where the fields are fa a and fb b;
+// idx = nx - i above, where a real field's column is the conjugate of its
+// column at -kx.  Column 0 of a real field is real (its imaginary part is
+// rounding only and is dropped); column nx/2 is zero (not built here).
+template <typename Real>
+__device__ __forceinline__ cplx<Real> pair_value(cplx<Real> a, cplx<Real> b, const PairSrc& ps,
+                                                 Real kx, bool mirror, bool col0) {
+  if (col0) {
+    a.y = 0;
+    b.y = 0;
+  }
+  cplx<Real> A = kx_factor(a, ps.fa, kx);
+  cplx<Real> B = ps.b >= 0 ? kx_factor(b, ps.fb, kx) : mk<Real>(0, 0);
+  if (mirror) {
+    A.y = -A.y;
+    B.y = -B.y;
+  }
+  return mk<Real>(A.x - B.y, A.y + B.x);
+}
+
+// Half-plane column of slot m of thread tr (columns tr + m TPR of the row):
+// slots m < ER/2 hold columns below nx/2, the others mirror columns.
+template <int LOG2NX>
+__device__ __forceinline__ int half_col(int tr, int m) {
+  constexpr int TPR = (1 << LOG2NX) / ER;
+  return m < ER / 2 ? tr + m * TPR : (TPR - tr) + (ER - 1 - m) * TPR;
+}
+
+// Input of transform q for row iy, read from the half planes in the tiled
+// layout (tiles of 2^lw columns by 2^lh rows, rows 2^lhw wide).
 template <typename Real, int LOG2NX>
-__device__ __forceinline__ void load_row(const cplx<Real>* __restrict__ plane, int iy, bool valid,
-                                         int tr, int lw, int lh, cplx<Real>* v) {
+__device__ __forceinline__ void load_pair_row(const cplx<Real>* __restrict__ planes, size_t psz,
+                                              int q, int iy, bool valid, int tr, const GridP& gp,
+                                              cplx<Real>* v) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER;
-  const size_t rb = ((size_t)(iy >> lh) << (LOG2NX + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  const PairSrc ps = pair_src(q);
+  const int lw = gp.tlw, lh = gp.tlh;
+  const size_t rb =
+      ((size_t)(iy >> lh) << (gp.lhw + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  const cplx<Real>* pa = planes + (size_t)ps.a * psz + rb;
+  const cplx<Real>* pb = planes + (size_t)(ps.b >= 0 ? ps.b : 0) * psz + rb;
+  const Real dkx = (Real)(6.283185307179586476925 / ((double)nx * gp.dx));
+  auto off = [&](int col) {
+    return ((size_t)(col >> lw) << (lw + lh)) + (col & ((1 << lw) - 1));
+  };
+  cplx<Real> a[ER], b[ER];
   if ((TPR & ((1 << lw) - 1)) == 0) {
-    // columns tr + m TPR: TPR / TW tiles further per slot
-    const cplx<Real>* p =
-        plane + rb + ((size_t)(tr >> lw) << (lw + lh)) + (tr & ((1 << lw) - 1));
+    // columns tr + m TPR and their mirrors: TPR / TW tiles apart per slot
+    const size_t ed = off(tr), em = off(TPR - tr), step = (size_t)TPR << lh;
 #pragma unroll
-    for (int m = 0; m < ER; ++m) v[m] = valid ? p[(size_t)m * TPR << lh] : mk<Real>(0, 0);
+    for (int m = 0; m < ER; ++m) {
+      const bool ok = valid && (m != ER / 2 || tr != 0);
+      const size_t e = m < ER / 2 ? ed + (size_t)m * step : em + (size_t)(ER - 1 - m) * step;
+      a[m] = ok ? pa[e] : mk<Real>(0, 0);
+      b[m] = (ok && ps.b >= 0) ? pb[e] : mk<Real>(0, 0);
+    }
   } else {
 #pragma unroll
     for (int m = 0; m < ER; ++m) {
-      const int ix = tr + m * TPR;
-      v[m] = valid ? plane[rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1))]
-                   : mk<Real>(0, 0);
+      const int col = half_col<LOG2NX>(tr, m);
+      const bool ok = valid && col < nx / 2;
+      a[m] = ok ? pa[off(col)] : mk<Real>(0, 0);
+      b[m] = (ok && ps.b >= 0) ? pb[off(col)] : mk<Real>(0, 0);
     }
+  }
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    const int col = half_col<LOG2NX>(tr, m);
+    v[m] = pair_value(a[m], b[m], ps, dkx * (Real)col, m >= ER / 2, m == 0 && tr == 0);
   }
 }
 
-// Direct global -> LDS loads of row iy of a plane into S (nx elements in
-// column order), issued by the TPR threads of a single-row block: 16 bytes
-// per lane (two float or one double element, adjacent within a tile), or 4
-// bytes per lane for float planes in one-column tiles.  Completion is
-// awaited with the vector-memory counter and a barrier before S is read.
+// A thread's own columns tr + m TPR (m < ER/2) of the two half planes of a
+// transform, loaded ahead of use.
+template <typename Real>
+struct PairRegs {
+  cplx<Real> a[ER / 2], b[ER / 2];
+};
+
+// Loads the own columns of transform q for row iy (zeros outside the grid).
 template <typename Real, int LOG2NX>
-__device__ __forceinline__ void stage_row(const cplx<Real>* __restrict__ plane, int iy,
-                                          const GridP& gp, cplx<Real>* S, int tr) {
-  constexpr int nx = 1 << LOG2NX, TPR = nx / ER, W = TPR / 64;
+__device__ __forceinline__ void load_pair_direct(const cplx<Real>* __restrict__ planes,
+                                                 size_t psz, int q, int iy, int tr,
+                                                 const GridP& gp, PairRegs<Real>& r) {
+  constexpr int nx = 1 << LOG2NX, TPR = nx / ER, H = ER / 2;
+  const PairSrc ps = pair_src(q);
+  const bool valid = iy >= 0 && iy < gp.ny;
+  const int lw = gp.tlw, lh = gp.tlh;
+  const size_t rb =
+      ((size_t)(iy >> lh) << (gp.lhw + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  const cplx<Real>* pa = planes + (size_t)ps.a * psz + rb;
+  const cplx<Real>* pb = planes + (size_t)(ps.b >= 0 ? ps.b : 0) * psz + rb;
+  const size_t ed = ((size_t)(tr >> lw) << (lw + lh)) + (tr & ((1 << lw) - 1));
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    size_t e;
+    if ((TPR & ((1 << lw) - 1)) == 0) {
+      e = ed + (size_t)m * ((size_t)TPR << lh);
+    } else {
+      const int col = tr + m * TPR;
+      e = ((size_t)(col >> lw) << (lw + lh)) + (col & ((1 << lw) - 1));
+    }
+    r.a[m] = valid ? pa[e] : mk<Real>(0, 0);
+    r.b[m] = (valid && ps.b >= 0) ? pb[e] : mk<Real>(0, 0);
+  }
+}
+
+// Input of transform q from the own columns in r: they are put in X (half
+// plane a at [0, nx/2), b at [nx/2, nx)) and, after a barrier, the mirror
+// columns are read from there, so that every half-plane element is read
+// from memory once.  The barrier before the writes separates this
+// transform from the previous one's LDS use.
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void build_pair_x(const PairRegs<Real>& r, int q, int tr,
+                                             const GridP& gp, cplx<Real>* v, cplx<Real>* X) {
+  constexpr int nx = 1 << LOG2NX, TPR = nx / ER, H = ER / 2;
+  const PairSrc ps = pair_src(q);
+  const Real dkx = (Real)(6.283185307179586476925 / ((double)nx * gp.dx));
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    X[tr + m * TPR] = r.a[m];
+    if (ps.b >= 0) X[nx / 2 + tr + m * TPR] = r.b[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    const int col = half_col<LOG2NX>(tr, m);
+    cplx<Real> a, b;
+    if (m < H) {
+      a = r.a[m];
+      b = r.b[m];
+    } else {
+      const bool ok = m != H || tr != 0;
+      a = ok ? X[col] : mk<Real>(0, 0);
+      b = (ok && ps.b >= 0) ? X[nx / 2 + col] : mk<Real>(0, 0);
+    }
+    v[m] = pair_value(a, b, ps, dkx * (Real)col, m >= H, m == 0 && tr == 0);
+  }
+}
+
+// Direct global -> LDS loads of the first nx/2 columns of row iy of a half
+// plane into S (column order), issued by the TPR threads of a single-row
+// block: 16 bytes per lane (two float or one double element, adjacent within
+// a tile), or 4 bytes per lane for float planes in one-column tiles.
+// Completion is awaited with the vector-memory counter and a barrier before
+// S is read.
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void stage_half_row(const cplx<Real>* __restrict__ plane, int iy,
+                                               const GridP& gp, cplx<Real>* S, int tr) {
+  constexpr int nx = 1 << LOG2NX, TPR = nx / ER, W = TPR / 64, NH = nx / 2;
   constexpr int cs = sizeof(cplx<Real>);
   const int lane = tr & 63, w = tr >> 6;
   const int lw = gp.tlw, lh = gp.tlh;
-  const size_t rb = ((size_t)(iy >> lh) << (LOG2NX + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
+  const size_t rb =
+      ((size_t)(iy >> lh) << (gp.lhw + lh)) + ((size_t)(iy & ((1 << lh) - 1)) << lw);
   typedef __attribute__((address_space(3))) void* lds_ptr;
   if (cs == 16 || lw >= 1) {
     constexpr int EPL = 16 / cs;       // elements per lane
     constexpr int PER = 64 * EPL;      // elements per wave instruction
 #pragma unroll
-    for (int c = w; c < nx / PER; c += W) {
+    for (int c = w; c < NH / PER; c += W) {
       const int ix = c * PER + lane * EPL;
       const cplx<Real>* src =
           plane + rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1));
@@ -255,8 +420,8 @@ __device__ __forceinline__ void stage_row(const cplx<Real>* __restrict__ plane, 
   } else {
     const Real* f = reinterpret_cast<const Real*>(plane);
 #pragma unroll
-    for (int c = w; c < 2 * nx / 64; c += W) {
-      const int qf = c * 64 + lane;    // scalar index within the row
+    for (int c = w; c < 2 * NH / 64; c += W) {
+      const int qf = c * 64 + lane;    // scalar index within the half row
       const int ix = qf >> 1;
       const size_t e = rb + ((size_t)(ix >> lw) << (lw + lh)) + (ix & ((1 << lw) - 1));
       __builtin_amdgcn_global_load_lds((const void*)(f + 2 * e + (qf & 1)),
@@ -265,46 +430,76 @@ __device__ __forceinline__ void stage_row(const cplx<Real>* __restrict__ plane, 
   }
 }
 
-// Where the next transform's row comes from (staged mode): plane index and
-// row, or no next transform (plane < 0).
+// Stages the inputs of transform q for row iy: half plane a into S[0, nx/2),
+// half plane b into S[nx/2, nx).
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void stage_pair(const cplx<Real>* __restrict__ planes, size_t psz,
+                                           int q, int iy, const GridP& gp, cplx<Real>* S,
+                                           int tr) {
+  const PairSrc ps = pair_src(q);
+  stage_half_row<Real, LOG2NX>(planes + (size_t)ps.a * psz, iy, gp, S, tr);
+  if (ps.b >= 0)
+    stage_half_row<Real, LOG2NX>(planes + (size_t)ps.b * psz, iy, gp, S + (1 << LOG2NX) / 2, tr);
+}
+
+// Input of transform q from its staged half rows.
+template <typename Real, int LOG2NX>
+__device__ __forceinline__ void read_pair_lds(const cplx<Real>* S, int q, int tr, const GridP& gp,
+                                              cplx<Real>* v) {
+  constexpr int nx = 1 << LOG2NX;
+  const PairSrc ps = pair_src(q);
+  const Real dkx = (Real)(6.283185307179586476925 / ((double)nx * gp.dx));
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    const int col = half_col<LOG2NX>(tr, m);
+    const bool ok = m != ER / 2 || tr != 0;
+    const cplx<Real> a = ok ? S[col] : mk<Real>(0, 0);
+    const cplx<Real> b = (ok && ps.b >= 0) ? S[nx / 2 + col] : mk<Real>(0, 0);
+    v[m] = pair_value(a, b, ps, dkx * (Real)col, m >= ER / 2, m == 0 && tr == 0);
+  }
+}
+
+// Where the next transform's input comes from (staged mode): transform
+// index and row, or no next transform (q < 0).
 struct NextRow {
-  int plane, iy;
+  int q, iy;
 };
 
-// Inverse transform along x of one plane for one row.  The thread
+// Inverse transform along x of transform q for one row.  The thread
 // coordinate is made opaque per call, so that addresses and LDS offsets are
 // recomputed per transform instead of being kept live across all six.
-// Staged mode: the row was loaded into S ahead of time; once every thread
-// has its values, the next transform's row is put in flight into S.
+// Staged mode: the input rows were loaded into S ahead of time; once every
+// thread has its values, the next transform's rows are put in flight into S.
 // Unstaged mode with lrow2 set: the exchanges alternate between lrow and
-// lrow2 (one barrier each), and a barrier after the row loads separates this
-// transform from the previous one.
+// lrow2 (one barrier each), the mirror columns of the input go through lrow2
+// before the first exchange writes lrow (build_pair_x), and the own columns
+// of the next transform are loaded into pre while this one runs.
 template <typename Real, int LOG2NX, bool STAGE>
 __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ planes, size_t psz,
-                                              int p, int iy, bool valid, int tr,
+                                              int q, int iy, bool valid, int tr,
                                               const GridP& gp, cplx<Real>* lrow, cplx<Real>* S,
                                               NextRow nxt, const cplx<Real>* __restrict__ tw,
-                                              cplx<Real>* v, cplx<Real>* lrow2 = nullptr) {
+                                              cplx<Real>* v, cplx<Real>* lrow2 = nullptr,
+                                              PairRegs<Real>* pre = nullptr) {
   int trv = tr;
   asm volatile("" : "+v"(trv));
   if constexpr (STAGE) {
-    constexpr int TPR = (1 << LOG2NX) / ER;
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < ER; ++m) v[m] = S[trv + m * TPR];
+    read_pair_lds<Real, LOG2NX>(S, q, trv, gp, v);
     __syncthreads();
-    if (nxt.plane >= 0) stage_row<Real, LOG2NX>(planes + (size_t)nxt.plane * psz, nxt.iy, gp, S, trv);
+    if (nxt.q >= 0) stage_pair<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, gp, S, trv);
     // after S: the LDS twiddles (nx/2) and the second exchange row; the two
     // barriers above separate this transform from the previous one
     constexpr int nx = 1 << LOG2NX;
     fft_seq<Real, LOG2NX, ER, 1, +1, true, true>(v, lrow, trv, S + nx, S + nx + nx / 2);
   } else {
-    load_row<Real, LOG2NX>(planes + (size_t)p * psz, iy, valid, trv, gp.tlw, gp.tlh, v);
     if (lrow2) {
-      __syncthreads();
+      build_pair_x<Real, LOG2NX>(*pre, q, trv, gp, v, lrow2);
+      if (nxt.q >= 0) load_pair_direct<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, trv, gp, *pre);
       fft_seq<Real, LOG2NX, ER, 1, +1, false, true>(v, lrow, trv, tw, lrow2);
     } else {
+      load_pair_row<Real, LOG2NX>(planes, psz, q, iy, valid, trv, gp, v);
       fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
     }
   }
@@ -320,8 +515,8 @@ __device__ __forceinline__ void load_row_twiddles(cplx<Real>* dst,
 }
 
 // The nine facet quantities of one row, in the order they become available:
-// planes 1-3 give the normal (slopes, Jacobian), plane 0 the position,
-// planes 4-5 the displacement over the pulse pair.
+// transforms 1-3 give the normal (slopes, Jacobian), transform 0 the
+// position, transforms 4-5 the displacement over the pulse pair.
 template <typename Real>
 struct RowFacets {
   Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
@@ -332,25 +527,26 @@ __device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes
                                            int iy, bool valid, int tr, const GridP& gp,
                                            cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr) {
+                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr,
+                                           PairRegs<Real>* pre = nullptr) {
   cplx<Real> v[ER];
   Real hx[ER], hy[ER], dxx[ER];
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
-                                     NextRow{2, iy_stage}, tw, v, lrow2);  // Dy + i h_x
+                                     NextRow{2, iy_stage}, tw, v, lrow2, pre);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
-                                     NextRow{3, iy_stage}, tw, v, lrow2);  // h_y + i Dx_x
+                                     NextRow{3, iy_stage}, tw, v, lrow2, pre);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     hy[m] = v[m].x;
     dxx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
-                                     NextRow{0, iy_stage}, tw, v, lrow2);  // Dx_y + i Dy_y
+                                     NextRow{0, iy_stage}, tw, v, lrow2, pre);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     const Real dxy = v[m].x, dyy = v[m].y;
@@ -370,17 +566,18 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
                                            int iy, bool valid, int tr, const GridP& gp,
                                            cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            int iy_next, const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr) {
+                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr,
+                                           PairRegs<Real>* pre = nullptr) {
   cplx<Real> v[ER];
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
-                                     NextRow{4, iy_stage}, tw, v, lrow2);  // h + i Dx
+                                     NextRow{4, iy_stage}, tw, v, lrow2, pre);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
-                                     NextRow{5, iy_stage}, tw, v, lrow2);  // dh + i dDx
+                                     NextRow{5, iy_stage}, tw, v, lrow2, pre);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.dh[m] = v[m].x;
@@ -388,7 +585,8 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
   }
   // the row after this one starts with plane 1 (iy_next < 0: none)
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
-                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v, lrow2);  // dDy
+                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v, lrow2,
+                                     pre);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
 }
@@ -413,7 +611,7 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   cplx<Real>* lrow2 = row_facets_pp(LOG2NX, sizeof(cplx<Real>))
                           ? reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)(RPB + rl) * lpad(nx)
                           : nullptr;
-  const size_t psz = (size_t)nx * ny;
+  const size_t psz = (size_t)ny << gp.lhw;
   // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
   // contiguous run of row chunks, so that the chunks sharing a plane tile
   // (and its cache lines) are read through the same L2 at about the same time.
@@ -421,12 +619,18 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   const int q = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
                                 : blockIdx.x;
 
+  // with two exchange rows, the own columns of each transform's input are
+  // loaded one transform ahead (first: transform 1 of the first row)
+  PairRegs<Real> pre;
+  if (row_facets_pp(LOG2NX, sizeof(cplx<Real>)))
+    load_pair_direct<Real, LOG2NX>(planes, psz, 1, q * RPB + rl, tr, gp, pre);
   for (int iy0 = q * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
-    const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB : -1;
+    const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB + rl : -1;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, lrow2);
+    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, lrow2,
+                                    &pre);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -438,7 +642,7 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
       }
     }
     row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
-                                    F, lrow2);
+                                    F, lrow2, &pre);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < ER; ++m) {
@@ -489,7 +693,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   win_init(w, rp, wp);
   uint32_t cnt[5] = {0, 0, 0, 0, 0};
   uint32_t overflow = 0;
-  const size_t psz = (size_t)nx * ny;
+  const size_t psz = (size_t)ny << gp.lhw;
   // Row walk of this band.  The rows of one plane tile (TH rows) are split
   // over M = TH / RPB bands that run on the same XCD (workgroups are dealt
   // to the XCDs round robin) and walk the same tile rows together, so each
@@ -516,7 +720,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   // staged rows are clamped into the grid (a row past the band end is
   // transformed but not scattered)
   if (STAGE) load_row_twiddles<Real, LOG2NX>(S + nx, tw);   // ordered by the first barrier
-  if (STAGE && n_steps > 0) stage_row<Real, LOG2NX>(planes + psz, min(row_begin, ny - 1), gp, S, tr);
+  if (STAGE && n_steps > 0) stage_pair<Real, LOG2NX>(planes, psz, 1, min(row_begin, ny - 1), gp, S, tr);
   for (int k = 0; k < n_steps; ++k) {
     const int iy0 = row_begin + k * step_rows;
     const int iy = iy0 + rl;
@@ -939,6 +1143,7 @@ static GridP with_tiles(const GridP& gp) {
   GridP g = gp;
   g.tlw = tile_lw(gp.log2ny, sizeof(cplx<Real>));
   g.tlh = tile_lh(gp.log2ny, sizeof(cplx<Real>));
+  g.lhw = half_lw(gp.log2nx, gp.log2ny, sizeof(cplx<Real>));
   return g;
 }
 
@@ -949,7 +1154,7 @@ static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, dou
   if constexpr (col_lds(L, cs) > kLdsBudget) {
     return hipErrorInvalidValue;
   } else {
-    const int strips = gp.nx / col_cpb(L, cs);
+    const int strips = (1 << half_lw(gp.log2nx, L, cs)) / col_cpb(L, cs);
     if (prepared)
       hipLaunchKernelGGL((colpass_kernel<Real, L, true>), dim3(2 * strips),
                          dim3(col_threads(L, cs)), col_lds(L, cs), st, (const cplx<Real>*)spec,
@@ -976,12 +1181,14 @@ hipError_t launch_colpass(const void* spec, void* planes, const GridP& gp, doubl
 
 template <typename Real>
 hipError_t launch_prepare_spectrum(const void* spec, void* out, const GridP& gp, hipStream_t st) {
-  const int cpb = col_cpb(gp.log2ny, sizeof(cplx<Real>));
-  const size_t n = (size_t)gp.nx * gp.ny;
+  constexpr int cs = sizeof(cplx<Real>);
+  const int cpb = col_cpb(gp.log2ny, cs);
+  const int lhw = half_lw(gp.log2nx, gp.log2ny, cs);
+  const size_t n = (size_t)gp.ny << lhw;
   const size_t want = (n + 255) / 256;
   const int blocks = (int)(want < 65536 ? want : 65536);
   hipLaunchKernelGGL(prepare_spectrum_kernel<Real>, dim3(blocks), dim3(256), 0, st,
-                     (const cplx<Real>*)spec, (cplx<Real>*)out, gp.nx, gp.ny, cpb);
+                     (const cplx<Real>*)spec, (cplx<Real>*)out, gp.nx, gp.ny, lhw, cpb);
   return hipGetLastError();
 }
 

@@ -58,6 +58,19 @@ __host__ __device__ constexpr int tile_lh(int log2ny, int cs) {
   return kTileElems / col_cpb(log2ny, cs) > 1 ? ilog2_c(kTileElems / col_cpb(log2ny, cs)) : 0;
 }
 
+// The column pass transforms the columns kx >= 0 only (the fields are real,
+// so a column kx < 0 is the conjugate of column -kx) and writes eight
+// half-width planes, one per y-dependence of the fields.  Their width is
+// nx/2, widened to one tile where nx/2 is narrower (columns past nx/2 are
+// written as zeros and never read).
+constexpr int kHalfPlanes = 8;
+__host__ __device__ constexpr int half_lw(int log2nx, int log2ny, int cs) {
+  return log2nx - 1 > tile_lw(log2ny, cs) ? log2nx - 1 : tile_lw(log2ny, cs);
+}
+__host__ __device__ constexpr size_t half_plane_elems(int log2nx, int log2ny, int cs) {
+  return (size_t)1 << (half_lw(log2nx, log2ny, cs) + log2ny);
+}
+
 // Row passes: ER values per thread, RPB rows per block.
 constexpr int kRowE = 8;
 __host__ __device__ constexpr int row_tpr(int log2nx) { return (1 << log2nx) / kRowE; }
@@ -71,10 +84,11 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
   return (size_t)row_rpb(log2nx) * lpad_c((size_t)1 << log2nx) * cs;
 }
 
-// Staging of the next plane row in LDS for the fused row pass (direct
-// global -> LDS loads while the current row transform runs), for single-row
-// blocks whose LDS allows it: after the transform row, one row of nx
-// elements, the first nx/2 twiddles e^{2 pi i k / nx} (the row transform's
+// Staging of the next transform's input in LDS for the fused row pass
+// (direct global -> LDS loads of the two half-plane rows it is built from
+// while the current row transform runs), for single-row blocks whose LDS
+// allows it: after the transform row, nx elements (two half rows), the
+// first nx/2 twiddles e^{2 pi i k / nx} (the row transform's
 // twiddles are read from LDS, so that no global load of the transform has
 // to wait behind the staged row) and a second transform row (the exchanges
 // alternate between the two, one barrier each).  The fused kernel keeps room

@@ -425,16 +425,19 @@ class Simulator:
             self._stream(stream))
 
     def prepare_spectrum(self, spec0, stream=None):
-        """The spectrum in the column-pass layout (a complex tensor of 2 nx ny
-        elements), for update_and_accumulate_prepared."""
+        """The spectrum in the column-pass layout (a complex tensor of
+        sim_prepared_spectrum_size bytes), for update_and_accumulate_prepared."""
         g = self.grid
-        n = sim_prepared_spectrum_size(self.ctx, g) // (16 if self.precision == SIM_PREC_FP64
-                                                         else 8)
+        n = self._prepared_elems()
         out = self.torch.empty(n, dtype=self.complex_dtype, device=self.device)
         sim_prepare_spectrum(self.ctx, g,
                              self._need(spec0, self.complex_dtype, (g.ny, g.nx), "spec0"),
                              out.data_ptr(), self._stream(stream))
         return out
+
+    def _prepared_elems(self):
+        cs = 16 if self.precision == SIM_PREC_FP64 else 8
+        return sim_prepared_spectrum_size(self.ctx, self.grid) // cs
 
     def update_and_accumulate_prepared(self, prepared, t, j, t_fast, counters=None,
                                        facet_code=None, stream=None):
@@ -443,7 +446,7 @@ class Simulator:
         g = self.grid
         sim_update_and_accumulate_prepared(
             self.ctx, self.grid,
-            self._need(prepared, self.complex_dtype, (2 * g.nx * g.ny,), "prepared"),
+            self._need(prepared, self.complex_dtype, (self._prepared_elems(),), "prepared"),
             self.radar, float(t), int(j),
             self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
             n_spec,
