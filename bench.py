@@ -25,13 +25,14 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 METRIC = "facet-updates/s + simulated IQ pulses/s (FP32+FP64-phase vs FP64, same GPU)"
 
 # Algorithmic HBM bytes per facet and launch of each kernel (FP32 context;
-# FP64 doubles them): the column pass reads the spectrum once (8 B) and writes
-# six packed complex planes (48 B); the fused row pass reads the six planes
-# back (48 B) and writes nothing per facet; on the split row path the facet
-# row pass reads the planes and writes nine facet fields (36 B), which the
-# facet accumulate reads back.
-ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 48, "fused_rowpass": 48,
-                       "surface_rowpass": 48 + 36, "accumulate_facets": 36}
+# FP64 doubles them): the column pass reads the prepared spectrum (the mode
+# pairs of the columns kx >= 0: 8 B) and writes eight half-width planes
+# (32 B); the fused row pass reads the half planes back (32 B) and writes
+# nothing per facet; on the split row path the facet row pass reads the half
+# planes and writes nine facet fields (36 B), which the facet accumulate
+# reads back.
+ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 32, "fused_rowpass": 32,
+                       "surface_rowpass": 32 + 36, "accumulate_facets": 36}
 
 # Counter measurements of the kernels of both contexts on this workload
 # (profiles/), valid only for the kernel sources they were taken on: HBM bytes

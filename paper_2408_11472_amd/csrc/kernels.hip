@@ -329,13 +329,29 @@ struct PairRegs {
   cplx<Real> a[ER / 2], b[ER / 2];
 };
 
-// Loads the own columns of transform q for row iy (zeros outside the grid).
+// Loads the own columns of transform q for row iy (zeros outside the grid)
+// into r, which holds those of transform q_cur of the same row: a half plane
+// the two share is kept instead of read again (the row order of the
+// transforms, 3 1 0 2 4 5, puts the two users of half planes 2, 0 and 1
+// next to each other).
 template <typename Real, int LOG2NX>
 __device__ __forceinline__ void load_pair_direct(const cplx<Real>* __restrict__ planes,
                                                  size_t psz, int q, int iy, int tr,
-                                                 const GridP& gp, PairRegs<Real>& r) {
+                                                 const GridP& gp, PairRegs<Real>& r,
+                                                 int q_cur = -1) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER, H = ER / 2;
   const PairSrc ps = pair_src(q);
+  // which of a, b is already in r (after moving it into place)
+  bool have_a = false, have_b = false;
+  if (q_cur == 3 && q == 1) {
+    have_a = true;                       // half plane 2
+  } else if (q_cur == 1 && q == 0) {
+#pragma unroll
+    for (int m = 0; m < H; ++m) r.a[m] = r.b[m];   // half plane 0
+    have_a = true;
+  } else if (q_cur == 0 && q == 2) {
+    have_b = true;                       // half plane 1
+  }
   const bool valid = iy >= 0 && iy < gp.ny;
   const int lw = gp.tlw, lh = gp.tlh;
   const size_t rb =
@@ -352,8 +368,8 @@ __device__ __forceinline__ void load_pair_direct(const cplx<Real>* __restrict__ 
       const int col = tr + m * TPR;
       e = ((size_t)(col >> lw) << (lw + lh)) + (col & ((1 << lw) - 1));
     }
-    r.a[m] = valid ? pa[e] : mk<Real>(0, 0);
-    r.b[m] = (valid && ps.b >= 0) ? pb[e] : mk<Real>(0, 0);
+    if (!have_a) r.a[m] = valid ? pa[e] : mk<Real>(0, 0);
+    if (!have_b) r.b[m] = (valid && ps.b >= 0) ? pb[e] : mk<Real>(0, 0);
   }
 }
 
@@ -496,7 +512,9 @@ __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ pla
   } else {
     if (lrow2) {
       build_pair_x<Real, LOG2NX>(*pre, q, trv, gp, v, lrow2);
-      if (nxt.q >= 0) load_pair_direct<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, trv, gp, *pre);
+      if (nxt.q >= 0)
+        load_pair_direct<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, trv, gp, *pre,
+                                       nxt.iy == iy ? q : -1);
       fft_seq<Real, LOG2NX, ER, 1, +1, false, true>(v, lrow, trv, tw, lrow2);
     } else {
       load_pair_row<Real, LOG2NX>(planes, psz, q, iy, valid, trv, gp, v);
@@ -514,68 +532,82 @@ __device__ __forceinline__ void load_row_twiddles(cplx<Real>* dst,
   for (int i = threadIdx.x; i < nx / 2; i += blockDim.x) dst[i] = tw[nx + i];
 }
 
-// The nine facet quantities of one row, in the order they become available:
-// transforms 1-3 give the normal (slopes, Jacobian), transform 0 the
-// position, transforms 4-5 the displacement over the pulse pair.
+// The nine facet quantities of one row.  The transforms run in the order
+// 3 1 0 2 (geometry: the normal needs 3, 1 and 2; 0 gives the position), then
+// 4 5 (displacement over the pulse pair); each quantity is handed to emit(i,
+// values) as soon as it is formed, i its index in the facet SoA.
 template <typename Real>
 struct RowFacets {
   Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
 };
 
-template <typename Real, int LOG2NX, bool STAGE>
-__device__ __forceinline__ void row_normal(const cplx<Real>* __restrict__ planes, size_t psz,
-                                           int iy, bool valid, int tr, const GridP& gp,
-                                           cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
-                                           const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr,
-                                           PairRegs<Real>* pre = nullptr) {
+struct NoEmit {
+  template <typename T>
+  __device__ void operator()(int, const T*) const {}
+};
+
+template <typename Real, int LOG2NX, bool STAGE, typename Emit>
+__device__ __forceinline__ void row_geometry(const cplx<Real>* __restrict__ planes, size_t psz,
+                                             int iy, bool valid, int tr, const GridP& gp,
+                                             cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
+                                             const cplx<Real>* __restrict__ tw,
+                                             RowFacets<Real>& F, Emit emit,
+                                             cplx<Real>* lrow2 = nullptr,
+                                             PairRegs<Real>* pre = nullptr) {
   cplx<Real> v[ER];
-  Real hx[ER], hy[ER], dxx[ER];
+  Real dxy[ER], dyy[ER], hx[ER];
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
+                                     NextRow{1, iy_stage}, tw, v, lrow2, pre);  // Dx_y + i Dy_y
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    dxy[m] = v[m].x;
+    dyy[m] = v[m].y;
+  }
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
-                                     NextRow{2, iy_stage}, tw, v, lrow2, pre);  // Dy + i h_x
+                                     NextRow{0, iy_stage}, tw, v, lrow2, pre);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.Dy[m] = v[m].x;
     hx[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
-                                     NextRow{3, iy_stage}, tw, v, lrow2, pre);  // h_y + i Dx_x
-#pragma unroll
-  for (int m = 0; m < ER; ++m) {
-    hy[m] = v[m].x;
-    dxx[m] = v[m].y;
-  }
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
-                                     NextRow{0, iy_stage}, tw, v, lrow2, pre);  // Dx_y + i Dy_y
-#pragma unroll
-  for (int m = 0; m < ER; ++m) {
-    const Real dxy = v[m].x, dyy = v[m].y;
-    // n = r_x x r_y with r_x = (1 + Dx_x, Dx_y, h_x), r_y = (Dx_y, 1 + Dy_y, h_y)
-    const Real nxn = dxy * hy[m] - hx[m] * ((Real)1 + dyy);
-    const Real nyn = hx[m] * dxy - ((Real)1 + dxx[m]) * hy[m];
-    const Real nzn = ((Real)1 + dxx[m]) * ((Real)1 + dyy) - dxy * dxy;
-    const Real inz = approx_rcp(nzn);
-    F.jac[m] = nzn;
-    F.sx[m] = -nxn * inz;
-    F.sy[m] = -nyn * inz;
-  }
-}
-
-template <typename Real, int LOG2NX, bool STAGE>
-__device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
-                                           int iy, bool valid, int tr, const GridP& gp,
-                                           cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
-                                           int iy_next, const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F, cplx<Real>* lrow2 = nullptr,
-                                           PairRegs<Real>* pre = nullptr) {
-  cplx<Real> v[ER];
+  emit(1, F.Dy);
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
-                                     NextRow{4, iy_stage}, tw, v, lrow2, pre);  // h + i Dx
+                                     NextRow{2, iy_stage}, tw, v, lrow2, pre);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     F.h[m] = v[m].x;
     F.Dx[m] = v[m].y;
   }
+  emit(0, F.Dx);
+  emit(2, F.h);
+  row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
+                                     NextRow{4, iy_stage}, tw, v, lrow2, pre);  // h_y + i Dx_x
+#pragma unroll
+  for (int m = 0; m < ER; ++m) {
+    const Real hy = v[m].x, dxx = v[m].y;
+    // n = r_x x r_y with r_x = (1 + Dx_x, Dx_y, h_x), r_y = (Dx_y, 1 + Dy_y, h_y)
+    const Real nxn = dxy[m] * hy - hx[m] * ((Real)1 + dyy[m]);
+    const Real nyn = hx[m] * dxy[m] - ((Real)1 + dxx) * hy;
+    const Real nzn = ((Real)1 + dxx) * ((Real)1 + dyy[m]) - dxy[m] * dxy[m];
+    const Real inz = approx_rcp(nzn);
+    F.jac[m] = nzn;
+    F.sx[m] = -nxn * inz;
+    F.sy[m] = -nyn * inz;
+  }
+  emit(3, F.sx);
+  emit(4, F.sy);
+  emit(5, F.jac);
+}
+
+template <typename Real, int LOG2NX, bool STAGE, typename Emit>
+__device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
+                                           int iy, bool valid, int tr, const GridP& gp,
+                                           cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
+                                           int iy_next, const cplx<Real>* __restrict__ tw,
+                                           RowFacets<Real>& F, Emit emit,
+                                           cplx<Real>* lrow2 = nullptr,
+                                           PairRegs<Real>* pre = nullptr) {
+  cplx<Real> v[ER];
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
                                      NextRow{5, iy_stage}, tw, v, lrow2, pre);  // dh + i dDx
 #pragma unroll
@@ -583,12 +615,15 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
     F.dh[m] = v[m].x;
     F.dDx[m] = v[m].y;
   }
-  // the row after this one starts with plane 1 (iy_next < 0: none)
+  emit(6, F.dDx);
+  emit(8, F.dh);
+  // the row after this one starts with transform 3 (iy_next < 0: none)
   row_transform<Real, LOG2NX, STAGE>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
-                                     NextRow{iy_next >= 0 ? 1 : -1, iy_next}, tw, v, lrow2,
+                                     NextRow{iy_next >= 0 ? 3 : -1, iy_next}, tw, v, lrow2,
                                      pre);  // dDy
 #pragma unroll
   for (int m = 0; m < ER; ++m) F.dDy[m] = v[m].x;
+  emit(7, F.dDy);
 }
 
 template <typename Real, int LOG2NX>
@@ -620,40 +655,26 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
                                 : blockIdx.x;
 
   // with two exchange rows, the own columns of each transform's input are
-  // loaded one transform ahead (first: transform 1 of the first row)
+  // loaded one transform ahead (first: transform 3 of the first row)
   PairRegs<Real> pre;
   if (row_facets_pp(LOG2NX, sizeof(cplx<Real>)))
-    load_pair_direct<Real, LOG2NX>(planes, psz, 1, q * RPB + rl, tr, gp, pre);
+    load_pair_direct<Real, LOG2NX>(planes, psz, 3, q * RPB + rl, tr, gp, pre);
   for (int iy0 = q * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
     const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB + rl : -1;
+    // each facet quantity is stored as soon as it is formed
+    auto emit = [&](int field, const Real* val) {
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < ER; ++m) out.p[field][(size_t)iy * nx + tr + m * TPR] = val[m];
+      }
+    };
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, lrow2,
-                                    &pre);
-    if (valid) {
-#pragma unroll
-      for (int m = 0; m < ER; ++m) {
-        const size_t o = (size_t)iy * nx + tr + m * TPR;
-        out.p[1][o] = F.Dy[m];
-        out.p[3][o] = F.sx[m];
-        out.p[4][o] = F.sy[m];
-        out.p[5][o] = F.jac[m];
-      }
-    }
+    row_geometry<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, emit,
+                                      lrow2, &pre);
     row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
-                                    F, lrow2, &pre);
-    if (valid) {
-#pragma unroll
-      for (int m = 0; m < ER; ++m) {
-        const size_t o = (size_t)iy * nx + tr + m * TPR;
-        out.p[0][o] = F.Dx[m];
-        out.p[2][o] = F.h[m];
-        out.p[6][o] = F.dDx[m];
-        out.p[7][o] = F.dDy[m];
-        out.p[8][o] = F.dh[m];
-      }
-    }
+                                    F, emit, lrow2, &pre);
   }
 }
 
@@ -720,7 +741,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   // staged rows are clamped into the grid (a row past the band end is
   // transformed but not scattered)
   if (STAGE) load_row_twiddles<Real, LOG2NX>(S + nx, tw);   // ordered by the first barrier
-  if (STAGE && n_steps > 0) stage_pair<Real, LOG2NX>(planes, psz, 1, min(row_begin, ny - 1), gp, S, tr);
+  if (STAGE && n_steps > 0) stage_pair<Real, LOG2NX>(planes, psz, 3, min(row_begin, ny - 1), gp, S, tr);
   for (int k = 0; k < n_steps; ++k) {
     const int iy0 = row_begin + k * step_rows;
     const int iy = iy0 + rl;
@@ -728,9 +749,10 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
     const int iy_stage = min(iy, ny - 1);
     const int iy_next = k + 1 < n_steps ? min(iy0 + step_rows + rl, ny - 1) : -1;
     RowFacets<Real> F;
-    row_normal<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, tw, F);
+    row_geometry<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, tw, F,
+                                      NoEmit());
     row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, iy_next,
-                                    tw, F);
+                                    tw, F, NoEmit());
     int key[ER];
     cplx<Real> cv[ER];
     // opaque row coordinates: the grid positions of the facets are
