@@ -40,14 +40,14 @@ ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 32, "fused_rowpass": 32,
 # copy, and VALU wave-instructions per launch (SQ_INSTS_VALU).
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "d08d5daab262b17a",
-    "fp32": {"traffic_bytes": {"surface_colpass": 1290e6, "surface_rowpass": 1410e6,
+    "source_sha": "efadf1de57b8fce5",
+    "fp32": {"traffic_bytes": {"surface_colpass": 820e6, "surface_rowpass": 1141e6,
                                "accumulate_facets": 606e6},
-             "valu_wave_instr": {"surface_colpass": 1.85e+08, "surface_rowpass": 1.01e+08,
+             "valu_wave_instr": {"surface_colpass": 1.13e+08, "surface_rowpass": 1.08e+08,
                                  "accumulate_facets": 8.43e+07}},
-    "fp64": {"traffic_bytes": {"surface_colpass": 2151e6, "surface_rowpass": 2824e6,
+    "fp64": {"traffic_bytes": {"surface_colpass": 1344e6, "surface_rowpass": 2282e6,
                                "accumulate_facets": 1210e6},
-             "valu_wave_instr": {"surface_colpass": 1.96e+08, "surface_rowpass": 1.03e+08,
+             "valu_wave_instr": {"surface_colpass": 1.2e+08, "surface_rowpass": 1.15e+08,
                                  "accumulate_facets": 1.01e+08}},
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
