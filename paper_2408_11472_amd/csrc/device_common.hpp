@@ -33,12 +33,15 @@ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk(a.x * s, a
 template <typename T>
 __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk(a.x, -a.y); }
 
-// Reciprocal and square root for amplitude-type quantities: the hardware
-// approximations (within about 1 ulp) in float, correctly rounded in double.
+// Reciprocal, square root and reciprocal square root for amplitude-type
+// quantities and spectral multipliers: the hardware approximations (within
+// about 1 ulp) in float, the library's double routines in double.
 __device__ __forceinline__ float approx_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double approx_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float approx_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double approx_sqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float approx_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double approx_rsqrt(double x) { return rsqrt(x); }
 
 // sin(pi x), cos(pi x) in the precision of the argument.
 __device__ __forceinline__ void sincos_pi(float x, float* s, float* c) { sincospif(x, s, c); }

@@ -156,7 +156,7 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       const int nys = iy < ny / 2 ? iy : iy - ny;
       const Real ky = (Real)dky * (Real)nys;
       const Real k2 = kxv * kxv + ky * ky;
-      const Real ik = k2 > (Real)0 ? rsqrt(k2) : (Real)0;
+      const Real ik = k2 > (Real)0 ? approx_rsqrt(k2) : (Real)0;
       Real r;
       switch (f) {
         case 0:
@@ -783,7 +783,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
 // ---------------------------------------------------------------------------
 // Scatterers from a facet SoA: band = contiguous facet range, chunks of
 // EA * blockDim facets.
-constexpr int EA = 4;
+constexpr int EA = 8;
 
 template <typename Real>
 __global__ void __launch_bounds__(acc_threads(sizeof(cplx<Real>)))
