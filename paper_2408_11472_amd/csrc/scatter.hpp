@@ -112,6 +112,58 @@ __device__ __forceinline__ void lds_add(cplx<Real>* p, cplx<Real> v) {
   atomicAdd(&p->y, v.y);
 }
 
+// Value of lane l xor 1 (CTRL 0xB1) or l xor 2 (CTRL 0x4E) within a quad.
+template <int CTRL>
+__device__ __forceinline__ int quad_swap(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float x) {
+  return __builtin_bit_cast(float, quad_swap<CTRL>(__builtin_bit_cast(int, x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)quad_swap<CTRL>((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)quad_swap<CTRL>((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// Adds v to win[idx] for every lane with idx >= 0; every lane of the wave
+// must call it.  LDS atomics cost per adding lane, and neighbouring facets
+// (neighbouring lanes) mostly fall into the same gate and Doppler bin: lanes
+// l and l xor 1, then l and l xor 2, with the same index are merged into the
+// lower one first.
+template <typename Real>
+__device__ __forceinline__ void quad_lds_add(cplx<Real>* win, int idx, cplx<Real> v) {
+  const int lane = threadIdx.x & 63;
+  {
+    const int pi = quad_swap<0xB1>(idx);
+    const Real px = quad_swap<0xB1>(v.x), py = quad_swap<0xB1>(v.y);
+    if (idx >= 0 && pi == idx) {
+      if (lane & 1) {
+        idx = -1;
+      } else {
+        v.x += px;
+        v.y += py;
+      }
+    }
+  }
+  {
+    const int pi = quad_swap<0x4E>(idx);
+    const Real px = quad_swap<0x4E>(v.x), py = quad_swap<0x4E>(v.y);
+    if (idx >= 0 && pi == idx) {
+      if (lane & 2) {
+        idx = -1;
+      } else {
+        v.x += px;
+        v.y += py;
+      }
+    }
+  }
+  if (idx >= 0) lds_add(&win[idx], v);
+}
+
 template <typename Real>
 __device__ void win_init(const WinCtx<Real>& w, const RadarP& rp, const WinP& wp) {
   const int n = rp.G * wp.WK;
@@ -176,9 +228,9 @@ __device__ void win_add(const WinCtx<Real>& w, const RadarP& rp, const WinP& wp,
     int gmin = 0x7fffffff, gmax = -1, d0 = 0, d1 = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+      const int g = key[e] >> lgN;
+      quad_lds_add(w.win, key[e] >= 0 ? g * WK + (key[e] & (N - 1)) : -1, cv[e]);
       if (key[e] >= 0) {
-        const int g = key[e] >> lgN;
-        lds_add(&w.win[(size_t)g * WK + (key[e] & (N - 1))], cv[e]);
         gmin = min(gmin, g);
         gmax = max(gmax, g);
       }
@@ -224,8 +276,7 @@ __device__ void win_add(const WinCtx<Real>& w, const RadarP& rp, const WinP& wp,
   if (active && rmin >= -WK / 2 && rmax < WK / 2) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (key[e] >= 0)
-        lds_add(&w.win[(size_t)(key[e] >> lgN) * WK + rel[e] + WK / 2], cv[e]);
+      quad_lds_add(w.win, key[e] >= 0 ? (key[e] >> lgN) * WK + rel[e] + WK / 2 : -1, cv[e]);
     __syncthreads();
     if (threadIdx.x == 0) {
       w.st[2] = min(w.st[2], gmin);
@@ -240,8 +291,7 @@ __device__ void win_add(const WinCtx<Real>& w, const RadarP& rp, const WinP& wp,
     const int c0 = ((rmin + rmax + 1) >> 1) - WK / 2;
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (key[e] >= 0)
-        lds_add(&w.win[(size_t)(key[e] >> lgN) * WK + rel[e] - c0], cv[e]);
+      quad_lds_add(w.win, key[e] >= 0 ? (key[e] >> lgN) * WK + rel[e] - c0 : -1, cv[e]);
     __syncthreads();
     if (threadIdx.x == 0) {
       w.st[0] = 1;
@@ -256,8 +306,11 @@ __device__ void win_add(const WinCtx<Real>& w, const RadarP& rp, const WinP& wp,
   for (int c0 = rmin; c0 <= rmax; c0 += WK) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (key[e] >= 0 && rel[e] >= c0 && rel[e] < c0 + WK)
-        lds_add(&w.win[(size_t)(key[e] >> lgN) * WK + rel[e] - c0], cv[e]);
+      quad_lds_add(w.win,
+                   key[e] >= 0 && rel[e] >= c0 && rel[e] < c0 + WK
+                       ? (key[e] >> lgN) * WK + rel[e] - c0
+                       : -1,
+                   cv[e]);
     __syncthreads();
     if (threadIdx.x == 0) {
       w.st[0] = 1;
