@@ -40,15 +40,15 @@ ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 32, "fused_rowpass": 32,
 # copy, and VALU wave-instructions per launch (SQ_INSTS_VALU).
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "efadf1de57b8fce5",
+    "source_sha": "afaa7b51b8052295",
     "fp32": {"traffic_bytes": {"surface_colpass": 820e6, "surface_rowpass": 1141e6,
                                "accumulate_facets": 606e6},
-             "valu_wave_instr": {"surface_colpass": 1.13e+08, "surface_rowpass": 1.08e+08,
-                                 "accumulate_facets": 8.43e+07}},
-    "fp64": {"traffic_bytes": {"surface_colpass": 1344e6, "surface_rowpass": 2282e6,
+             "valu_wave_instr": {"surface_colpass": 1.02e+08, "surface_rowpass": 1.08e+08,
+                                 "accumulate_facets": 8.72e+07}},
+    "fp64": {"traffic_bytes": {"surface_colpass": 1344e6, "surface_rowpass": 2283e6,
                                "accumulate_facets": 1210e6},
              "valu_wave_instr": {"surface_colpass": 1.2e+08, "surface_rowpass": 1.15e+08,
-                                 "accumulate_facets": 1.01e+08}},
+                                 "accumulate_facets": 1.11e+08}},
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
 
