@@ -288,7 +288,8 @@ def test_full_run_small_256(prec, pcode, npdt):
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
-@pytest.mark.parametrize("nx,ny", [(64, 32), (256, 256), (8192, 32), (32, 16384), (1024, 64)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (256, 256), (8192, 32), (32, 16384),
+                                   (1024, 64)])
 def test_prepared_spectrum_gives_the_same_update(prec, pcode, npdt, nx, ny):
     """The column pass reading the prepared spectrum computes exactly what it
     computes from the FFT-order spectrum."""
