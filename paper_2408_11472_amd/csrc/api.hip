@@ -354,11 +354,11 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
 // Row path of the fused call: the fused row pass (facets never leave the
 // chip), or the facet row pass into the workspace followed by the facet
 // accumulate.  Automatic choice: the split path.  The fused row kernel holds
-// nine facet fields per value slot in registers (about 250 VGPRs in float,
+// nine facet fields per value slot in registers (about 245 VGPRs in float,
 // spills in double and for 8192-wide rows), so a CU runs one block of it;
 // the two split kernels keep several blocks per CU and measure faster even
-// with the facet round trip through HBM (4096^2 float: 652 vs 721 us per
-// update; double: 1.28 vs 2.28 ms).
+// with the facet round trip through HBM (4096^2 float: 0.62 vs 0.68 ms per
+// update for the row pass and accumulate; double: 1.18 vs 2.30 ms).
 bool use_split(const sim_ctx* c, const sim_grid* g) {
   (void)g;
   if (c->row_path == SIM_ROW_PATH_FUSED) return false;
