@@ -155,8 +155,10 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       const int iy = sv + m * TPS;
       const int nys = iy < ny / 2 ? iy : iy - ny;
       const Real ky = (Real)dky * (Real)nys;
+      // 1/|k|; the offset changes no k2 > 0 (k2 >= dk^2) and keeps the zero
+      // mode (whose value is zero) finite
       const Real k2 = kxv * kxv + ky * ky;
-      const Real ik = k2 > (Real)0 ? approx_rsqrt(k2) : (Real)0;
+      const Real ik = approx_rsqrt(k2 + (Real)1e-30);
       Real r;
       switch (f) {
         case 0:
@@ -168,7 +170,11 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
         default: r = dcw * ky * ik; break;   // 2, 7
       }
       const cplx<Real> z = st[m];
-      v[m] = imag ? mk<Real>(-r * z.y, r * z.x) : mk<Real>(r * z.x, r * z.y);
+      v[m] = mk<Real>(r * z.x, r * z.y);
+    }
+    if (imag) {   // (uniform) i r z
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = mk<Real>(-v[m].y, v[m].x);
     }
     fft_seq<Real, LOG2NY, E, CPB, +1>(v, lds + (ixv - strip * CPB), sv, tw);
     // tiled plane layout (TW = CPB columns by TH rows per tile)
