@@ -40,14 +40,14 @@ ALG_BYTES_PER_FACET = {"surface_colpass": 8 + 32, "fused_rowpass": 32,
 # copy, and VALU wave-instructions per launch (SQ_INSTS_VALU).
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "afaa7b51b8052295",
-    "fp32": {"traffic_bytes": {"surface_colpass": 820e6, "surface_rowpass": 1141e6,
+    "source_sha": "b0be18267d4431c3",
+    "fp32": {"traffic_bytes": {"surface_colpass": 823e6, "surface_rowpass": 1141e6,
                                "accumulate_facets": 606e6},
-             "valu_wave_instr": {"surface_colpass": 1.02e+08, "surface_rowpass": 1.08e+08,
+             "valu_wave_instr": {"surface_colpass": 9.99e+07, "surface_rowpass": 1.08e+08,
                                  "accumulate_facets": 8.72e+07}},
-    "fp64": {"traffic_bytes": {"surface_colpass": 1344e6, "surface_rowpass": 2283e6,
+    "fp64": {"traffic_bytes": {"surface_colpass": 1345e6, "surface_rowpass": 2283e6,
                                "accumulate_facets": 1210e6},
-             "valu_wave_instr": {"surface_colpass": 1.2e+08, "surface_rowpass": 1.15e+08,
+             "valu_wave_instr": {"surface_colpass": 1.16e+08, "surface_rowpass": 1.15e+08,
                                  "accumulate_facets": 1.11e+08}},
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9   # one wave64 VALU instruction per CU per clock
