@@ -556,6 +556,35 @@ class Simulator:
         return t_fast, self.segments_to_iq(t_fast, y, stream=stream)
 
 
+def check_batch_buffers(grids, radars, updates, specs, T, Y, complex_dtype):
+    """Validate the per-member buffers of a batch run before any launch: one
+    spectrum, one T_fast and (when given) one Y per member, each a contiguous
+    tensor of the batch's complex dtype with that member's shape (spectrum
+    [ny][nx], T_fast [U + 1][G][N], Y [U n_fast][G]), on a GPU.  The C side
+    reads R pointers and trusts every buffer's size, so a short list or a
+    wrong shape must never reach it.  Raises ValueError."""
+    R = len(grids)
+    if len(specs) != R or len(T) != R or (Y is not None and len(Y) != R):
+        raise ValueError(f"batch of {R} members: got {len(specs)} spectra, {len(T)} T_fast"
+                         + ("" if Y is None else f", {len(Y)} Y") + " buffers")
+    want = []
+    for r in range(R):
+        g, rr, u = grids[r], radars[r], int(updates[r])
+        want += [(r, "spec", specs[r], (g.ny, g.nx)),
+                 (r, "t_fast", T[r], (u + 1, rr.n_gates, rr.n_doppler))]
+        if Y is not None:
+            want.append((r, "y", Y[r], (u * rr.n_fast, rr.n_gates)))
+    for r, name, x, shape in want:
+        if x.dtype != complex_dtype or not x.is_contiguous():
+            raise ValueError(f"member {r} {name}: expected a contiguous {complex_dtype} tensor")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"member {r} {name}: expected shape {tuple(shape)}, got "
+                             f"{tuple(x.shape)}")
+    for r, name, x, _ in want:
+        if not x.is_cuda:
+            raise ValueError(f"member {r} {name}: expected a CUDA tensor")
+
+
 class Batch:
     """Independent realisations run together on one context (update-major on
     one stream, optionally as one replayed HIP graph).  ``members`` is a list
@@ -609,11 +638,10 @@ class Batch:
     def run(self, specs, T, Y=None, use_graph=False):
         """Run the batch on the batch's own stream (ordered after the current
         stream's work, and the current stream waits for it)."""
+        check_batch_buffers(self.grids, self.radars, self.updates, specs, T, Y,
+                            self.complex_dtype)
         cur = self.torch.cuda.current_stream(self.device)
         self.stream.wait_stream(cur)
-        for x in list(specs) + list(T) + (list(Y) if Y is not None else []):
-            if not x.is_cuda or x.dtype != self.complex_dtype or not x.is_contiguous():
-                raise ValueError("batch buffers must be contiguous complex CUDA tensors")
         sim_batch_run(self.batch, [x.data_ptr() for x in specs], [x.data_ptr() for x in T],
                       None if Y is None else [x.data_ptr() for x in Y], use_graph,
                       self.stream.cuda_stream)

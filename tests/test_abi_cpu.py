@@ -59,3 +59,38 @@ def test_host_side_argument_checks():
     assert lib.sim_segments_to_iq(None, ctypes.byref(r), None, 2, None, None) == s.SIM_ERR_ARG
     assert lib.sim_destroy(None) == s.SIM_OK
     assert lib.sim_set_workspace(None, None, 0) == s.SIM_ERR_ARG
+
+
+def test_batch_buffers_are_checked_before_any_launch():
+    """Short lists and wrong shapes raise ValueError on the host (the C side
+    would read past the pointer arrays or write past the buffers)."""
+    import torch
+    from paper_2408_11472_amd import simradar as s
+    from paper_2408_11472_amd import workloads
+    wls = [workloads.tiny(nx=32, ny=16, n_gates=8, n_doppler=16, n_fast=16, n_updates=2),
+           workloads.tiny(nx=16, ny=64, n_gates=4, n_doppler=8, n_fast=8, n_updates=3)]
+    grids = [s.grid_struct(w.grid) for w in wls]
+    radars = [s.radar_struct(w.radar) for w in wls]
+    ups = [w.n_updates for w in wls]
+    cd = torch.complex64
+    specs = [torch.zeros((w.grid.ny, w.grid.nx), dtype=cd) for w in wls]
+    T = [torch.zeros((w.n_updates + 1, w.radar.n_gates, w.radar.n_doppler), dtype=cd)
+         for w in wls]
+    Y = [torch.zeros((w.n_pulses, w.radar.n_gates), dtype=cd) for w in wls]
+    with pytest.raises(ValueError, match="batch of 2 members"):
+        s.check_batch_buffers(grids, radars, ups, specs[:1], T, Y, cd)
+    with pytest.raises(ValueError, match="batch of 2 members"):
+        s.check_batch_buffers(grids, radars, ups, specs, T, Y[:1], cd)
+    bad_T = [T[0], torch.zeros((3, 4, 8), dtype=cd)]
+    with pytest.raises(ValueError, match="member 1 t_fast: expected shape"):
+        s.check_batch_buffers(grids, radars, ups, specs, bad_T, Y, cd)
+    bad_Y = [torch.zeros((31, 8), dtype=cd), Y[1]]
+    with pytest.raises(ValueError, match="member 0 y: expected shape"):
+        s.check_batch_buffers(grids, radars, ups, specs, T, bad_Y, cd)
+    with pytest.raises(ValueError, match="member 0 spec: expected a contiguous"):
+        s.check_batch_buffers(grids, radars, ups, [specs[0].t(), specs[1]], T, Y, cd)
+    # right shapes on the host: refused as not on a GPU
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        s.check_batch_buffers(grids, radars, ups, specs, T, Y, cd)
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        s.check_batch_buffers(grids, radars, ups, specs, T, None, cd)

@@ -26,7 +26,8 @@ import oracle.iq as oiq
 import oracle.scatter as osc
 import oracle.surface as osurf
 from paper_2408_11472_amd import inputs, workloads
-from tests.gpu_helpers import print_case, rel_l2, rounded_facets
+from tests.gpu_helpers import (continuous_coordinates, expected_flips, explain_mismatches,
+                               print_case, rel_l2, rounded_facets)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -55,13 +56,6 @@ def _row_grid(grid, iy):
     """The one-row grid whose only row is row iy of ``grid`` (same origin
     arithmetic as the whole grid: y_origin + iy dy)."""
     return dataclasses.replace(grid, ny=1, y_origin=grid.y_origin + iy * grid.dy)
-
-
-def _edge_distance(fac, grid, radar, t):
-    dx, dy, dz, r, r2 = osc.pulse_pair_ranges(fac, grid, radar, t)
-    xi = osc.gate_coordinate(r, radar)
-    u = osc.doppler_cycles(r, r2, radar) * radar.n_doppler
-    return np.minimum(np.abs(xi - np.round(xi)), np.abs((u + 0.5) - np.round(u + 0.5)))
 
 
 @pytest.mark.parametrize("which,prec", CASES)
@@ -158,20 +152,24 @@ def test_full_size_update_matches_oracle_samples(which, prec):
     assert rel_l2(T_s[j].cpu().numpy(), T_ref) <= (1e-12 if fp64 else 1e-5)
 
     # fused indices on the sampled rows against the oracle's own facets:
-    # mismatches only at gate/bin edges
+    # mismatches only at a threshold of the oracle's decisions, their count
+    # within the bound from the measured coordinate error
     code_fr = code_f[rows].cpu().numpy()
     code_or = np.empty_like(code_ref)
+    cref, cgpu = [], []
     for i, iy in enumerate(rows):
         sub = {k: ref[k][i:i + 1] for k in osurf.FACET_FIELDS}
         code_or[i] = osc.scatterers(sub, _row_grid(g, iy), r, t)[0][0]
-    bad = code_fr != code_or
-    if bad.any():
-        dist = np.concatenate([
-            _edge_distance({k: ref[k][i:i + 1] for k in osurf.FACET_FIELDS},
-                           _row_grid(g, iy), r, t)[0] for i, iy in enumerate(rows)
-        ]).reshape(bad.shape)
-        assert np.all(dist[bad] < (1e-6 if fp64 else 1e-3)), dist[bad].max()
-    assert int(bad.sum()) <= max(2, bad.size // 2000)
+        cref.append(continuous_coordinates(sub, _row_grid(g, iy), r, t))
+        cgpu.append(continuous_coordinates({k: got[k][i:i + 1] for k in osurf.FACET_FIELDS},
+                                           _row_grid(g, iy), r, t))
+    coords_ref = tuple(np.concatenate([c[m] for c in cref]) for m in range(4))
+    coords_gpu = tuple(np.concatenate([c[m] for c in cgpu]) for m in range(4))
+    n_bad = explain_mismatches(code_fr, code_or, coords_ref, 1e-6 if fp64 else 1e-4,
+                               1e-9 if fp64 else 1e-4, 1e-12 if fp64 else 1e-6)
+    n_exp = expected_flips(coords_gpu, coords_ref, code_or >= 0)
+    print("sampled-row index mismatches", n_bad, "expected", round(n_exp, 2), flush=True)
+    assert n_bad <= 2 + 3.0 * n_exp, (n_bad, n_exp)
     sim.close()
 
 

@@ -1,0 +1,261 @@
+"""The differentiable chain at the 2048 x 2048-facet gradient workload (17
+spectra, 4096 pulses, 128 gates x 256 bins), whole, against the FP64 oracle.
+
+* Same facets (the oracle's own surface at every update, given to both): the
+  forward T_fast, Y, waveform P and loss L, and the gradients dL/dh, dL/dsx,
+  dL/dsy of every facet of every update from the autograd wrapper (hand
+  adjoint kernels), FP64 context, against oracle.adjoint.gradients.
+* Central finite differences of the GPU FP64 forward on 64 seeded random
+  facets (random update, away from gate and bin edges) against the GPU
+  adjoint.
+* End to end from the spectrum (the GPU's own surface update feeds the
+  chain) in both contexts against the oracle chain.
+
+The target waveform is the oracle's waveform of the same workload with
+another seed (8), as the workload defines it.
+"""
+import numpy as np
+import pytest
+
+import oracle.adjoint as oad
+import oracle.scatter as osc
+import oracle.surface as osurf
+from paper_2408_11472_amd import inputs, workloads
+from tests.gpu_helpers import continuous_coordinates, print_case, print_precision, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+_C = {}
+TARGET_SEED = 8
+
+
+def _setup():
+    """Workload, spectrum, oracle facets of every update, the oracle forward
+    (T, Y, P, L) and the target.  The oracle spectra are evaluated in worker
+    processes (they are independent of each other)."""
+    if "facets" not in _C:
+        import oracle.iq as oiq
+        from tests import oracle_jobs
+        wl = workloads.gradient_2048()
+        g, r = wl.grid, wl.radar
+        times = [wl.update_time(j) for j in range(wl.n_spec)]
+
+        def spectrum(seed):
+            return inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh,
+                                       wl.sea.peak_wavelength, seed, wl.sea.swell)
+        spec8 = spectrum(TARGET_SEED)
+        spec = spectrum(wl.sea.seed)
+        with oracle_jobs.pool(2 * wl.n_spec) as ex:
+            j8 = [ex.submit(oracle_jobs.spectrum_update, spec8, g, r, t) for t in times]
+            j7 = [ex.submit(oracle_jobs.spectrum_update, spec, g, r, t, True) for t in times]
+            T8 = np.stack([f.result()[0] for f in j8])
+            res = [f.result() for f in j7]
+        # target: the oracle's multi-look waveform of the seed-8 sea
+        target = oad.waveform(oiq.segments_to_iq(T8, r.n_fast, r.window))
+        T = np.stack([x[0] for x in res])
+        Y = oiq.segments_to_iq(T, r.n_fast, r.window)
+        P = oad.waveform(Y)
+        _C.update(wl=wl, times=times, spec=spec, target=target,
+                  facets=[x[1] for x in res], T=T, Y=Y, P=P, L=oad.loss(P, target))
+    return _C
+
+
+def _oracle_gradients():
+    """The oracle's hand adjoint of the loss (Y_bar, T_bar, then the facet
+    gradients of every update in worker processes)."""
+    c = _setup()
+    if "grads" not in c:
+        from tests import oracle_jobs
+        wl = c["wl"]
+        r = wl.radar
+        Ybar = oad.loss_grad_y(c["Y"], c["target"])
+        Tbar = oad.segments_to_iq_adjoint(Ybar, wl.n_spec, r.n_doppler, r.n_fast, r.window)
+        with oracle_jobs.pool(wl.n_spec) as ex:
+            jobs = [ex.submit(oracle_jobs.facet_gradients, f, wl.grid, r, t, Tbar[j])
+                    for j, (f, t) in enumerate(zip(c["facets"], c["times"]))]
+            c["grads"] = [f.result() for f in jobs]
+    return c
+
+
+def _gpu_chain(sim, fac_stack, times, target_t, need_grad=True):
+    """Forward (T, Y, P, L) through the C ABI calls and the gradients through
+    the autograd wrapper (hand adjoint kernels)."""
+    from paper_2408_11472_amd.autograd import FIXED_FIELDS, waveform_loss
+    n_spec = len(times)
+    T = sim.empty_spectra(n_spec)
+    for j in range(n_spec):
+        sim.range_doppler_accumulate({k: fac_stack[k][j] for k in fac_stack}, times[j], j, T)
+    Y = sim.segments_to_iq(T)
+    P, L = sim.waveform_loss(Y, target_t)
+    out = {"T": T, "Y": Y, "P": P, "L": float(L)}
+    if need_grad:
+        h = fac_stack["h"].clone().requires_grad_(True)
+        sx = fac_stack["sx"].clone().requires_grad_(True)
+        sy = fac_stack["sy"].clone().requires_grad_(True)
+        fixed = {k: fac_stack[k] for k in FIXED_FIELDS}
+        Lw = waveform_loss(h, sx, sy, sim, fixed, times, target_t)
+        gh, gsx, gsy = torch.autograd.grad(Lw, (h, sx, sy))
+        out.update(h=gh, sx=gsx, sy=gsy, L_autograd=float(Lw.detach()))
+    torch.cuda.synchronize()
+    return out
+
+
+def _stack(facet_list, dtype):
+    return {k: torch.as_tensor(np.stack([f[k] for f in facet_list]), dtype=dtype, device="cuda")
+            for k in osurf.FACET_FIELDS}
+
+
+def test_gradient_2048_forward_same_facets_fp64():
+    from paper_2408_11472_amd import simradar
+    print_case("gradient chain forward, same facets, fp64")
+    c = _setup()
+    wl = c["wl"]
+    sim = simradar.Simulator(wl.grid, wl.radar, simradar.SIM_PREC_FP64)
+    fs = _stack(c["facets"], torch.float64)
+    tgt = torch.as_tensor(c["target"], dtype=torch.float64, device="cuda")
+    got = _gpu_chain(sim, fs, c["times"], tgt, need_grad=False)
+    errs = {"T_fast": rel_l2(got["T"].cpu().numpy(), c["T"]),
+            "Y": rel_l2(got["Y"].cpu().numpy(), c["Y"]),
+            "P": rel_l2(got["P"].cpu().numpy(), c["P"]),
+            "L": abs(got["L"] - c["L"]) / abs(c["L"])}
+    for k, v in errs.items():
+        print_precision("gradient_2048", "fp64 same facets", k, v)
+        assert v <= 1e-12, (k, v)
+    sim.close()
+
+
+def test_gradient_2048_gradients_same_facets_fp64():
+    from paper_2408_11472_amd import simradar
+    print_case("gradient chain adjoint, same facets, fp64")
+    c = _oracle_gradients()
+    wl = c["wl"]
+    sim = simradar.Simulator(wl.grid, wl.radar, simradar.SIM_PREC_FP64)
+    fs = _stack(c["facets"], torch.float64)
+    tgt = torch.as_tensor(c["target"], dtype=torch.float64, device="cuda")
+    got = _gpu_chain(sim, fs, c["times"], tgt)
+    errs = {"L(autograd)": abs(got["L_autograd"] - c["L"]) / abs(c["L"])}
+    for name in ("h", "sx", "sy"):
+        ref = np.stack([g[name] for g in c["grads"]])
+        errs[f"dL/d{name}"] = rel_l2(got[name].cpu().numpy(), ref)
+    for k, v in errs.items():
+        print_precision("gradient_2048", "fp64 same facets", k, v)
+        assert v <= 1e-10, (k, v)
+    sim.close()
+
+
+def _pick_facets(c, n, seed):
+    """n random (update, row, column) facets that are illuminated and sit at
+    least 1e-3 of a gate or bin away from an edge."""
+    wl = c["wl"]
+    g, r = wl.grid, wl.radar
+    rng = np.random.default_rng(seed)
+    picks = []
+    while len(picks) < n:
+        j = int(rng.integers(wl.n_spec))
+        iy, ix = int(rng.integers(g.ny)), int(rng.integers(g.nx))
+        f = {k: c["facets"][j][k][iy:iy + 1, ix:ix + 1] for k in osurf.FACET_FIELDS}
+        sub = workloads.Grid(nx=1, ny=1, dx=g.dx, dy=g.dy, x_origin=g.x_origin + ix * g.dx,
+                             y_origin=g.y_origin + iy * g.dy, gravity=g.gravity, cwm=g.cwm)
+        code, _ = osc.scatterers(f, sub, r, c["times"][j])
+        if code[0, 0] < 0:
+            continue
+        xi, ub, _, _ = continuous_coordinates(f, sub, r, c["times"][j])
+        dg = abs(xi[0, 0] - round(xi[0, 0]))
+        db = abs((ub[0, 0] + 0.5) - round(ub[0, 0] + 0.5))
+        if min(dg, db) > 1e-3:
+            picks.append((j, iy, ix))
+    return picks
+
+
+def test_gradient_2048_finite_differences_gpu_fp64():
+    """dL/dtheta of the GPU adjoint against central differences of the GPU
+    forward on 64 facets.  The ~815 km range carries a ~1.2e-10 m rounding
+    floor in double (~7e-8 rad of carrier phase), so the height step stays
+    well above it: theta = h uses the fourth-order stencil with a 2e-5 m step
+    (truncation ~1e-9, rounding ~6e-6 relative), sx and sy the second-order
+    one with a 1e-6 step."""
+    from paper_2408_11472_amd import simradar
+    print_case("gradient FD fp64")
+    c = _setup()
+    wl = c["wl"]
+    sim = simradar.Simulator(wl.grid, wl.radar, simradar.SIM_PREC_FP64)
+    fs = _stack(c["facets"], torch.float64)
+    tgt = torch.as_tensor(c["target"], dtype=torch.float64, device="cuda")
+    base = _gpu_chain(sim, fs, c["times"], tgt)
+    T0 = base["T"]
+    picks = _pick_facets(c, 64, seed=2024)
+    worst = {"h": 0.0, "sx": 0.0, "sy": 0.0}
+    setting = {"h": (2e-5, 3e-5), "sx": (1e-6, 1e-5), "sy": (1e-6, 1e-5)}
+    checked = 0
+    for (j, iy, ix) in picks:
+        fj = {k: fs[k][j].clone() for k in fs}
+        for name in ("h", "sx", "sy"):
+            eps, tol = setting[name]
+            v0 = float(fj[name][iy, ix])
+
+            def L_at(delta):
+                fj[name][iy, ix] = v0 + delta
+                T = T0.clone()
+                T[j].zero_()
+                sim.range_doppler_accumulate(fj, c["times"][j], j, T)
+                _, L = sim.waveform_loss(sim.segments_to_iq(T), tgt)
+                return float(L)
+            if name == "h":
+                fd = (8.0 * (L_at(eps) - L_at(-eps)) - (L_at(2 * eps) - L_at(-2 * eps))) \
+                    / (12.0 * eps)
+            else:
+                fd = (L_at(eps) - L_at(-eps)) / (2.0 * eps)
+            fj[name][iy, ix] = v0
+            adj = float(base[name][j, iy, ix])
+            # the difference carries the rounding of L (~1e-15 relative: the
+            # window sums of T are not ordered) over 2 eps; gradients too
+            # small to resolve above that floor are not compared
+            floor = 1e-14 * abs(base["L"]) / eps
+            if abs(adj) < 100.0 * floor:
+                continue
+            err = (abs(fd - adj) - floor) / abs(adj)
+            worst[name] = max(worst[name], err)
+            checked += 1
+            assert err <= tol, (j, iy, ix, name, fd, adj)
+    for name, v in worst.items():
+        print_precision("gradient_2048", "fp64", f"FD vs adjoint dL/d{name} (max rel, 64 facets)",
+                        v)
+    assert checked >= 150, checked
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_2048_chain_end_to_end(prec):
+    """The chain fed by the GPU's own surface update of every spectrum
+    against the oracle chain on the oracle's surface."""
+    from paper_2408_11472_amd import simradar
+    print_case("gradient chain end to end", prec)
+    c = _oracle_gradients()
+    wl = c["wl"]
+    g, r = wl.grid, wl.radar
+    fp64 = prec == "fp64"
+    sim = simradar.Simulator(g, r, simradar.SIM_PREC_FP64 if fp64 else
+                             simradar.SIM_PREC_FP32_PHASE64)
+    dtype = torch.float64 if fp64 else torch.float32
+    spec_t = torch.as_tensor(c["spec"].astype(np.complex128 if fp64 else np.complex64),
+                             device="cuda")
+    fs = {k: torch.empty((wl.n_spec, g.ny, g.nx), dtype=dtype, device="cuda")
+          for k in osurf.FACET_FIELDS}
+    for j, t in enumerate(c["times"]):
+        sim.surface_update(spec_t, t, 1.0 / r.prf_hz, out={k: fs[k][j] for k in fs})
+    tgt = torch.as_tensor(c["target"], dtype=dtype, device="cuda")
+    got = _gpu_chain(sim, fs, c["times"], tgt)
+    tol = 1e-9 if fp64 else 1e-3
+    errs = {"T_fast": rel_l2(got["T"].cpu().numpy(), c["T"]),
+            "Y": rel_l2(got["Y"].cpu().numpy(), c["Y"]),
+            "P": rel_l2(got["P"].cpu().numpy(), c["P"]),
+            "L": abs(got["L"] - c["L"]) / abs(c["L"])}
+    for name in ("h", "sx", "sy"):
+        ref = np.stack([gg[name] for gg in c["grads"]])
+        errs[f"dL/d{name}"] = rel_l2(got[name].cpu().numpy(), ref)
+    for k, v in errs.items():
+        print_precision("gradient_2048", f"{prec} end to end", k, v)
+    for k, v in errs.items():
+        assert v <= (tol if not k.startswith("dL") else (1e-9 if fp64 else 1e-3)), (k, v)
+    sim.close()

@@ -5,13 +5,13 @@ Tolerances (relative L2 over all complex entries unless stated):
 * same inputs, FP32 context with FP64 range/phase: indices bit-exact, values
   <= 1e-5 (float amplitudes, float sums of ~1e3 terms, float transforms);
 * end to end from the spectrum, FP64: values <= 1e-9, index mismatches only
-  for facets within 1e-6 of a gate/bin edge;
+  for facets within 1e-6 of a gate/bin edge (or of the fold and facing
+  thresholds);
 * end to end, FP32: values <= 5e-3 (float surface heights move the carrier
   phase by ~1e-4 rad and flip facets that sit on gate/bin edges), mismatching
-  indices only for facets within 1e-3 of an edge.
+  indices only for facets within 1e-4 of an edge, their count bounded by the
+  measured coordinate error.
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -20,7 +20,8 @@ import oracle.iq as oiq
 import oracle.scatter as osc
 import oracle.surface as osurf
 from paper_2408_11472_amd import inputs, workloads
-from tests.gpu_helpers import print_case, rel_l2, rounded_facets, to_torch_facets
+from tests.gpu_helpers import (continuous_coordinates, expected_flips, explain_mismatches,
+                               print_case, rel_l2, rounded_facets, to_torch_facets)
 
 pytestmark = pytest.mark.gpu
 
@@ -212,21 +213,19 @@ def test_surface_update_long_pair_interval(prec, pcode, npdt):
 
 # ---------------------------------------------------------------- end to end
 
-def _count_edge_ok(code, code_ref, fac, wl, t, edge_tol):
-    """Every index mismatch must sit within edge_tol of a gate or bin edge in
-    the oracle's continuous coordinates."""
-    bad = np.argwhere(code != code_ref)
-    if bad.size == 0:
-        return 0
-    dx, dy, dz, r, r2 = osc.pulse_pair_ranges(fac, wl.grid, wl.radar, t)
-    xi = osc.gate_coordinate(r, wl.radar)
-    u = osc.doppler_cycles(r, r2, wl.radar) * wl.radar.n_doppler
-    for iy, ix in bad:
-        dg = abs(xi[iy, ix] - round(xi[iy, ix]))
-        db = abs((u[iy, ix] + 0.5) - round(u[iy, ix] + 0.5))
-        assert min(dg, db) < edge_tol or code_ref[iy, ix] in (-2, -4) or code[iy, ix] in (-2, -4), \
-            (iy, ix, code[iy, ix], code_ref[iy, ix], dg, db)
-    return len(bad)
+def _mismatch_check(code, code_ref, fac_ref, fac_gpu, wl, t, fp64):
+    """Every index mismatch sits on a threshold of the oracle's decision
+    (gate or bin edge within 1e-4 in float / 1e-6 in double, |J| < 1e-4 /
+    1e-9, |q|/R < 1e-6 / 1e-12), and the count stays within a bound computed
+    from the measured coordinate error of the GPU facets."""
+    coords = continuous_coordinates(fac_ref, wl.grid, wl.radar, t)
+    n_bad = explain_mismatches(code, code_ref, coords, 1e-6 if fp64 else 1e-4,
+                               1e-9 if fp64 else 1e-4, 1e-12 if fp64 else 1e-6)
+    coords_gpu = continuous_coordinates(fac_gpu, wl.grid, wl.radar, t)
+    n_exp = expected_flips(coords_gpu, coords, code_ref >= 0)
+    print(f"index mismatches {n_bad}, expected {n_exp:.2f}", flush=True)
+    assert n_bad <= 2 + 3.0 * n_exp, (n_bad, n_exp)
+    return n_bad
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
@@ -256,8 +255,11 @@ def test_update_and_accumulate_end_to_end(prec, pcode, npdt, which):
     fac = osurf.facets(spec, wl.grid, t, 1.0 / wl.radar.prf_hz)
     T_ref, code_ref, cnt_ref = osc.accumulate(fac, wl.grid, wl.radar, t)
     code = code.cpu().numpy()
-    n_bad = _count_edge_ok(code, code_ref, fac, wl, t, 1e-6 if prec == "fp64" else 1e-3)
-    assert n_bad <= (2 if prec == "fp64" else max(4, code.size // 2000)), n_bad
+    # the facets of the same kernels (the fused call's split row path writes
+    # exactly these) give the measured coordinate error
+    fg = sim.surface_update(spec_t, t, 1.0 / wl.radar.prf_hz)
+    fac_gpu = {k: v.cpu().numpy().astype(np.float64) for k, v in fg.items()}
+    _mismatch_check(code, code_ref, fac, fac_gpu, wl, t, prec == "fp64")
     err = rel_l2(Tt.cpu().numpy()[j], T_ref)
     assert err <= (1e-9 if prec == "fp64" else 5e-3), err
     assert int(cnt.cpu().numpy()[:5].sum()) == wl.n_facets

@@ -94,3 +94,17 @@ def test_chain_gradient_by_central_differences(field, eps, tol):
         if checked == 12:
             break
     assert checked >= 8
+
+
+def test_waveform_loss_and_gradient_by_hand():
+    """A 2-pulse, 2-gate IQ matrix worked out by hand:
+    Y = [[1+i, 2], [0, 3i]]  ->  P = ((|1+i|^2 + 0) / 2, (4 + 9) / 2) = (1, 6.5);
+    target (0, 6)  ->  L = 1^2 + 0.5^2 = 1.25;
+    Y_bar = 2 (P - target)[g] * 2 Y / 2 = (2 Y[:, 0], Y[:, 1])."""
+    Y = np.array([[1 + 1j, 2.0], [0.0, 3j]])
+    target = np.array([0.0, 6.0])
+    P = oad.waveform(Y)
+    np.testing.assert_allclose(P, [1.0, 6.5], rtol=1e-15)
+    assert abs(oad.loss(P, target) - 1.25) <= 1e-15
+    Yb = oad.loss_grad_y(Y, target)
+    np.testing.assert_allclose(Yb, np.array([[2 + 2j, 2.0], [0.0, 3j]]), rtol=1e-15)
