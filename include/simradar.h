@@ -16,10 +16,12 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - All data pointers are DEVICE pointers owned by the caller.  The library
- *    never allocates in a compute call; its only device allocation is a
- *    twiddle table made by sim_create.  Scratch memory (surface transform
- *    planes, per-band partial spectra) is caller-provided through
- *    sim_set_workspace.
+ *    allocates no device memory: its twiddle tables are static arrays of the
+ *    code object (one copy per device), filled by the first sim_create on
+ *    each device.  Scratch memory (surface transform planes, per-band partial
+ *    spectra) is caller-provided through sim_set_workspace.  No compute call
+ *    creates HIP objects (the profiling events are made by
+ *    sim_profile_enable).
  *  - Every compute call is asynchronous on the HIP stream passed as `stream`
  *    (NULL = the default stream).  Argument and shape checks are synchronous
  *    and return a status; nothing is launched when a check fails.  A launch
@@ -45,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 2
+#define SIM_ABI_VERSION 3
 
 typedef enum sim_status {
   SIM_OK = 0,
@@ -143,12 +145,13 @@ int sim_abi_version(void);
 /* Static text of a status code. */
 const char *sim_status_string(sim_status status);
 
-/* Create a context on HIP device `device` with the given precision; makes
- * the twiddle table (the only allocation the library does).  *ctx is NULL
- * on failure. */
+/* Create a context on HIP device `device` (made current) with the given
+ * precision.  The first call on a device resolves the device addresses of
+ * the library's static tables and fills the twiddles (a synchronous copy).
+ * *ctx is NULL on failure. */
 sim_status sim_create(sim_ctx **ctx, int device, sim_precision precision);
 
-/* Release the context and its twiddle table.  NULL is accepted. */
+/* Release the context (and its profiling events).  NULL is accepted. */
 sim_status sim_destroy(sim_ctx *ctx);
 
 /* Precision of a context. */
@@ -321,7 +324,9 @@ sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
  * While enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the stream it is launched on; sim_profile_read waits
  * for the last event and returns, per kernel kind, the summed duration and
- * the launch count since the profile was (re)enabled. */
+ * the launch count since the profile was (re)enabled.  The events come from
+ * a pool of 8192 pairs that the first sim_profile_enable creates; launches
+ * beyond it are not timed and are counted in `dropped`. */
 #define SIM_KERNEL_SURFACE_COLPASS 0      /* spectrum -> 8 half planes, FFT in y */
 #define SIM_KERNEL_SURFACE_ROWPASS 1      /* FFT along x -> facet SoA            */
 #define SIM_KERNEL_FUSED_ROWPASS 2        /* FFT along x + scatterers + windows  */
@@ -335,9 +340,11 @@ sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 typedef struct sim_kernel_times {
   double ms[SIM_KERNEL_KINDS];
   uint64_t launches[SIM_KERNEL_KINDS];
+  uint64_t dropped;           /* launches not timed: the event pool was full */
 } sim_kernel_times;
 
-/* enable != 0 starts (and clears) the record; 0 stops recording. */
+/* enable != 0 starts (and clears) the record, creating the event pool on
+ * the first call; 0 stops recording. */
 sim_status sim_profile_enable(sim_ctx *ctx, int enable);
 
 /* Synchronise on the recorded events and sum them into *out. */

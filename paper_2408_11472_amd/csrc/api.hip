@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/simradar.h"
@@ -23,18 +24,28 @@ using simk::WinP;
 struct sim_ctx {
   int device;
   sim_precision prec;
-  void* tw;            // kTwSize complex, precision of the context
+  const void* tw;      // the device's twiddle table of the context's precision
   void* ws;
   size_t ws_bytes;
   int row_bands;   // tuning: bands of the fused row pass (0 = default)
   int row_path;    // tuning: row path of the fused call (SIM_ROW_PATH_*)
   bool capturing;  // a batch is being captured into a graph
-  // per-kernel timing
+  // per-kernel timing: a pool of event pairs made by sim_profile_enable, so
+  // that no compute call creates events
   bool profiling;
   std::vector<hipEvent_t> ev;   // pool, pairs (start, stop)
   std::vector<int> kind;        // kernel kind of each recorded pair
   size_t used;                  // pairs recorded
+  uint64_t dropped;             // launches not timed (pool exhausted)
 };
+
+// Twiddle tables (entries [M, 2M) hold e^{+2 pi i m / M} for every power of
+// two M <= kTwMax), one per precision, in the code object: every device the
+// library runs on holds its own copy, filled once by the first sim_create on
+// that device.  Host code uses them only through the addresses returned by
+// hipGetSymbolAddress for that device.
+__device__ __align__(256) float g_tw32[2 * simk::kTwEntries];
+__device__ __align__(256) double g_tw64[2 * simk::kTwEntries];
 
 namespace {
 
@@ -44,6 +55,7 @@ constexpr int kSlots = 4;                      // window slots per band
 constexpr int kMaxBands = 512;       // bands (blocks) of the fused row pass
 constexpr int kAccBands = 512;       // bands (blocks) of the facet accumulate
 constexpr int kWsBands = kAccBands > kMaxBands ? kAccBands : kMaxBands;
+constexpr int kProfilePairs = 8192;  // timed launches per profile record
 
 bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(long v) {
@@ -222,6 +234,50 @@ void make_twiddles(Real* host) {
   }
 }
 
+// Per-device state of the library's static device memory, set up once per
+// device (by the first sim_create on it, with the device current).
+constexpr int kMaxDevices = 64;
+struct DeviceState {
+  bool ready;
+  void* tw32;
+  void* tw64;
+};
+std::mutex g_dev_mutex;
+DeviceState g_dev[kMaxDevices];
+
+template <typename Real>
+sim_status fill_twiddles(void* dst) {
+  const size_t n = 2 * (size_t)simk::kTwEntries;
+  Real* host = new (std::nothrow) Real[n];
+  if (!host) return SIM_ERR_DEVICE;
+  make_twiddles<Real>(host);
+  const sim_status s = dev_err(hipMemcpy(dst, host, n * sizeof(Real), hipMemcpyHostToDevice),
+                               "twiddle table upload");
+  delete[] host;
+  return s;
+}
+
+// Resolve the device addresses of the static tables on `device` (current)
+// and fill the twiddles; idempotent.
+sim_status device_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return SIM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_dev_mutex);
+  DeviceState& d = g_dev[device];
+  if (d.ready) return SIM_OK;
+  void* a = nullptr;
+  void* b = nullptr;
+  sim_status s = dev_err(hipGetSymbolAddress(&a, HIP_SYMBOL(g_tw32)), "twiddle table address");
+  if (s == SIM_OK)
+    s = dev_err(hipGetSymbolAddress(&b, HIP_SYMBOL(g_tw64)), "twiddle table address");
+  if (s == SIM_OK) s = fill_twiddles<float>(a);
+  if (s == SIM_OK) s = fill_twiddles<double>(b);
+  if (s != SIM_OK) return s;
+  d.tw32 = a;
+  d.tw64 = b;
+  d.ready = true;
+  return SIM_OK;
+}
+
 bool facets_ok(const sim_facets* f) {
   if (!f) return false;
   void* const p[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
@@ -267,7 +323,9 @@ sim_status common_checks(sim_ctx* c, const sim_grid* g, const sim_radar* r, WsLa
   return SIM_OK;
 }
 
-// Bracket one kernel launch with events when profiling is on.
+// Bracket one kernel launch with events when profiling is on.  The events
+// come from the pool made by sim_profile_enable; when it is exhausted the
+// launch is not timed and counted as dropped.
 struct ProfScope {
   sim_ctx* c;
   hipStream_t st;
@@ -276,14 +334,9 @@ struct ProfScope {
       : c(c_), st(st_), on(c_->profiling && !c_->capturing) {
     if (!on) return;
     if (c->used * 2 + 2 > c->ev.size()) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-        on = false;
-        return;
-      }
-      c->ev.push_back(a);
-      c->ev.push_back(b);
-      c->kind.push_back(0);
+      c->dropped++;
+      on = false;
+      return;
     }
     c->kind[c->used] = kind;
     (void)hipEventRecord(c->ev[2 * c->used], st);
@@ -459,54 +512,30 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   // the attribute only raises the dynamic-LDS cap; a runtime that does not
   // need it may refuse it, which is harmless
   if (simk::init_kernel_attributes(lds_max) != hipSuccess) (void)hipGetLastError();
+  const sim_status sd = device_setup(device);
+  if (sd != SIM_OK) return sd;
   sim_ctx* c = new (std::nothrow) sim_ctx;
   if (!c) return SIM_ERR_DEVICE;
   c->device = device;
   c->prec = precision;
   c->ws = nullptr;
   c->ws_bytes = 0;
-  c->tw = nullptr;
+  c->tw = precision == SIM_PREC_FP64 ? g_dev[device].tw64 : g_dev[device].tw32;
   c->profiling = false;
   c->used = 0;
+  c->dropped = 0;
   c->row_bands = 0;
   c->row_path = SIM_ROW_PATH_AUTO;
   c->capturing = false;
-  const size_t cs = csize(c);
-  const size_t bytes = (size_t)simk::kTwEntries * cs;
-  if (dev(hipMalloc(&c->tw, bytes)) != SIM_OK) {
-    delete c;
-    return SIM_ERR_DEVICE;
-  }
-  char* host = new (std::nothrow) char[bytes];
-  if (!host) {
-    (void)hipFree(c->tw);
-    delete c;
-    return SIM_ERR_DEVICE;
-  }
-  if (precision == SIM_PREC_FP64)
-    make_twiddles<double>((double*)host);
-  else
-    make_twiddles<float>((float*)host);
-  const sim_status e = dev(hipMemcpy(c->tw, host, bytes, hipMemcpyHostToDevice));
-  delete[] host;
-  if (e != SIM_OK) {
-    (void)hipFree(c->tw);
-    delete c;
-    return SIM_ERR_DEVICE;
-  }
   *ctx = c;
   return SIM_OK;
 }
 
 sim_status sim_destroy(sim_ctx* ctx) {
   if (!ctx) return SIM_OK;
-  sim_status s = SIM_OK;
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
-  if (ctx->tw) {
-    if (use_device(ctx) != SIM_OK || hipFree(ctx->tw) != hipSuccess) s = SIM_ERR_DEVICE;
-  }
   delete ctx;
-  return s;
+  return SIM_OK;
 }
 
 sim_status sim_get_precision(const sim_ctx* ctx, sim_precision* precision) {
@@ -808,8 +837,27 @@ sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
 
 sim_status sim_profile_enable(sim_ctx* ctx, int enable) {
   if (!ctx) return SIM_ERR_ARG;
+  if (enable && ctx->ev.empty()) {
+    sim_status s = use_device(ctx);
+    if (s != SIM_OK) return s;
+    ctx->ev.reserve(2 * (size_t)kProfilePairs);
+    for (int i = 0; i < 2 * kProfilePairs; ++i) {
+      hipEvent_t e;
+      s = dev(hipEventCreate(&e));
+      if (s != SIM_OK) {
+        for (hipEvent_t x : ctx->ev) (void)hipEventDestroy(x);
+        ctx->ev.clear();
+        return s;
+      }
+      ctx->ev.push_back(e);
+    }
+    ctx->kind.assign(kProfilePairs, 0);
+  }
   ctx->profiling = enable != 0;
-  if (enable) ctx->used = 0;
+  if (enable) {
+    ctx->used = 0;
+    ctx->dropped = 0;
+  }
   return SIM_OK;
 }
 
@@ -819,6 +867,7 @@ sim_status sim_profile_read(sim_ctx* ctx, sim_kernel_times* out) {
     out->ms[k] = 0.0;
     out->launches[k] = 0;
   }
+  out->dropped = ctx->dropped;
   if (ctx->used == 0) return SIM_OK;
   sim_status s = use_device(ctx);
   if (s != SIM_OK) return s;
@@ -895,10 +944,18 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
   }
   sim_status first = SIM_OK;
   for (int l = 0; l < NL && first == SIM_OK; ++l) {
-    sim_ctx lc = *c;            // same device and twiddles, the lane's workspace
+    sim_ctx lc;                 // same device, twiddles and tuning, the lane's workspace
+    lc.device = c->device;
+    lc.prec = c->prec;
+    lc.tw = c->tw;
     lc.ws = (char*)c->ws + b->lane_off[l];
     lc.ws_bytes = b->lane_bytes[l];
+    lc.row_bands = c->row_bands;
+    lc.row_path = c->row_path;
+    lc.capturing = c->capturing;
     lc.profiling = false;
+    lc.used = 0;
+    lc.dropped = 0;
     hipStream_t ls = b->lane_st[l];
     for (int j = 0; j <= jmax && first == SIM_OK; ++j) {
       for (int r = 0; r < R; ++r) {

@@ -85,7 +85,8 @@ class sim_facets(ctypes.Structure):
 
 
 class sim_kernel_times(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
+                ("dropped", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -299,8 +300,13 @@ def sim_profile_enable(ctx, enable: bool) -> None:
 
 
 def sim_profile_read(ctx) -> dict:
+    """{kernel kind: (summed ms, launches)}; raises when launches went untimed
+    (more than the event pool holds), since the sums would be partial."""
     out = sim_kernel_times()
     _check("sim_profile_read", _lib.sim_profile_read(ctx, ctypes.byref(out)))
+    if out.dropped:
+        raise RuntimeError(f"sim_profile_read: {int(out.dropped)} launches were not timed "
+                           "(event pool exhausted); profile fewer launches at a time")
     return {k: (out.ms[i], int(out.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
 
 
