@@ -40,17 +40,20 @@ def flags():
 
 def build(verbose: bool = False) -> str:
     """Compile every source to an object and link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
     cc = hipcc()
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the sources compile independently: one compiler process each
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for cmd, _ in zip(cmds, ex.map(lambda c: subprocess.run(c, check=True), cmds)):
+            if verbose:
+                print(" ".join(cmd), flush=True)
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
