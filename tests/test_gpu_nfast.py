@@ -1,0 +1,75 @@
+"""Regular mode and the fast-mode approximation on the GPU (Sec. III.A,
+Sec. IV.B).
+
+* Regular mode = the library's path with n_fast = 1 (a surface update at
+  every pulse): its IQ must be the oracle's, which for n_fast = 1 is the
+  per-pulse coherent sum of the scatterers of each gate (pinned on the CPU
+  against a brute-force sum): <= 1e-9 (FP64) and 5e-3 (FP32 with double
+  range and phase) relative L2, the end-to-end bounds.
+* Fast mode against the regular mode on one scene: the multi-look power
+  waveform of each n_fast must stay within the speckle confidence interval
+  of the regular mode's (Fig. 6: similar for every n_fast tested), and the
+  total power within 4 of its standard deviations (eq. (1) conserves the
+  variance on average).  The z values use the combined standard deviation of
+  two independent runs, which overstates that of the difference of two runs
+  on one surface (positively correlated), so the Bonferroni bound at 1e-3
+  is conservative.
+"""
+import numpy as np
+import pytest
+
+import oracle.fastmode as ofm
+from paper_2408_11472_amd import inputs, nfast, workloads
+from tests.gpu_helpers import print_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny,cwm", [(64, 64, 1), (32, 128, 0)])
+def test_regular_mode_matches_oracle(prec, nx, ny, cwm):
+    from paper_2408_11472_amd import simradar
+    print_case("regular mode", prec, nx, ny, cwm)
+    fp64 = prec == "fp64"
+    wl = workloads.tiny(nx=nx, ny=ny, spacing=2.0, n_gates=32, n_doppler=2, n_fast=1,
+                        n_updates=24, cwm=cwm)
+    g, r = wl.grid, wl.radar
+    spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, wl.sea.swh, wl.sea.peak_wavelength,
+                               wl.sea.seed)
+    T_ref, Y_ref = ofm.simulate(spec, g, r, wl.n_updates)
+    sim = simradar.Simulator(g, r, simradar.SIM_PREC_FP64 if fp64 else
+                             simradar.SIM_PREC_FP32_PHASE64)
+    T, Y = sim.run(torch.as_tensor(spec.astype(np.complex128 if fp64 else np.complex64),
+                                   device="cuda"), wl.n_updates)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy()
+    # with n_fast = 1, pulse x is spectrum x summed over its bins
+    assert np.allclose(Y_ref, T_ref[:-1].sum(axis=-1), rtol=0, atol=1e-12 * np.abs(Y_ref).max())
+    err = rel_l2(Yh, Y_ref)
+    print(f"regular mode {prec} {nx}x{ny}: IQ rel L2 {err:.2e}", flush=True)
+    assert err <= (1e-9 if fp64 else 5e-3), err
+    sim.close()
+
+
+def test_fast_mode_waveform_within_speckle_interval():
+    from paper_2408_11472_amd import simradar
+    print_case("fast vs regular waveform")
+    scene = nfast.sweep_scene(nx=512, n_pulses=2000)
+    n_fasts = (100, 250, 500, 1000)
+    res = nfast.sweep(scene, n_fasts, simradar.SIM_PREC_FP32_PHASE64, torch, with_iq=True,
+                      max_lag=8)
+    reg = res[1]
+    print(f"regular: {reg['spectra']} spectra, {reg['gpu_s'] * 1e3:.2f} ms", flush=True)
+    for nf in n_fasts:
+        r = res[nf]
+        bound = nfast.sigma_of_z_bound(r["gates_compared"], 1e-3)
+        print(f"n_fast {nf}: {r['gpu_s'] * 1e3:.2f} ms (x{r['speedup']:.1f}), max|z| "
+              f"{r['max_abs_z']:.2f} (bound {bound:.2f}), rms z {r['rms_z']:.2f}, waveform "
+              f"rel L2 {r['waveform_rel_l2']:.3f}, power ratio {r['power_ratio']:.4f} +- "
+              f"{r['power_ratio_sigma']:.4f}, IQ correlation max diff "
+              f"{r['iq_correlation_max_diff']:.3f}", flush=True)
+        assert r["gates_compared"] >= 8
+        assert r["max_abs_z"] <= bound, (nf, r["max_abs_z"], bound)
+        assert abs(r["power_ratio"] - 1.0) <= 4.0 * r["power_ratio_sigma"], nf
+        assert r["speedup"] > 1.0, nf
