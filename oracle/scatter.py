@@ -112,6 +112,29 @@ def doppler_bin(u, n_doppler):
     return np.mod(kk, n_doppler)
 
 
+def amplitude_tables(fac, grid, radar, dx, dy, dz, r, tables):
+    """Complex amplitude with the tabulated NRCS and/or antenna pattern
+    (oracle.tables; a missing table falls back to its closed form):
+    a = sqrt(sigma0 A) G (H / R)^2."""
+    from . import tables as otab
+    sx, sy, jac = fac["sx"], fac["sy"], fac["jac"]
+    theta, tan2 = otab.local_incidence(fac, dx, dy, dz)
+    if tables.nrcs is not None:
+        sigma0 = otab.nrcs_lookup(theta, tables)
+    else:
+        cos2 = 1.0 / (1.0 + tan2)
+        sigma0 = radar.fresnel_sq / (radar.mss * cos2 * cos2) * np.exp(-tan2 / radar.mss)
+    area = jac * np.sqrt(1.0 + sx * sx + sy * sy) * grid.dx * grid.dy
+    if tables.antenna is not None:
+        u, v = otab.line_of_sight(dx, dy, r)
+        ga = otab.antenna_lookup(u, v, tables)
+    else:
+        gamma = (2.0 / np.log(2.0)) * np.sin(0.5 * radar.beamwidth_3db) ** 2
+        ga = np.exp(-(2.0 / gamma) * (dx * dx + dy * dy) / (r * r))
+    hr = radar.altitude / r
+    return np.sqrt(sigma0 * area) * ga * hr * hr
+
+
 def amplitude(fac, grid, radar, dx, dy, dz, r):
     """Real amplitude a of each facet (see module header)."""
     sx, sy, jac = fac["sx"], fac["sy"], fac["jac"]
@@ -138,8 +161,9 @@ def carrier_phase(r, radar):
     return np.exp(-2j * np.pi * frac)
 
 
-def scatterers(fac, grid, radar, t):
-    """Per-facet code (g N + bin, or a negative drop code) and amplitude C."""
+def scatterers(fac, grid, radar, t, tables=None):
+    """Per-facet code (g N + bin, or a negative drop code) and amplitude C
+    (closed forms, or the look-up tables of oracle.tables when given)."""
     G, N = radar.n_gates, radar.n_doppler
     fac = {k: np.asarray(v, dtype=np.float64) for k, v in fac.items()}
     finite = np.ones(fac["h"].shape, dtype=bool)
@@ -161,7 +185,10 @@ def scatterers(fac, grid, radar, t):
         code[finite & folded] = CODE_FOLDED
         code[finite & ~folded & ~in_win] = CODE_OUT_OF_WINDOW
         code[finite & ~folded & in_win & ~(q > 0.0)] = CODE_BACKFACING
-        a = amplitude(safe, grid, radar, dx, dy, dz, r)
+        if tables is None:
+            a = amplitude(safe, grid, radar, dx, dy, dz, r)
+        else:
+            a = amplitude_tables(safe, grid, radar, dx, dy, dz, r, tables)
         c = np.where(ok, a * carrier_phase(r, radar), 0.0)
     return code, c
 
@@ -188,8 +215,8 @@ def counters(code):
     }
 
 
-def accumulate(fac, grid, radar, t):
+def accumulate(fac, grid, radar, t, tables=None):
     """One Doppler spectrum [G, N] from a facet set at pulse time t, plus the
     per-facet codes and the drop counters."""
-    code, c = scatterers(fac, grid, radar, t)
+    code, c = scatterers(fac, grid, radar, t, tables)
     return rasterize(code, c, radar), code, counters(code)
