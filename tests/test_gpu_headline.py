@@ -178,13 +178,27 @@ def test_two_sided_spectrum_surface_update(prec, nx, ny, cwm):
                              device="cuda")
     out = sim.surface_update(spec_t, t, dt)
     torch.cuda.synchronize()
-    tol = 1e-11 if fp64 else 2e-5
+    # The oracle forms the pair displacement as the difference of two whole
+    # surfaces one pulse apart (Algorithm 1 regenerates the surface at the
+    # second pulse), so in double its increments carry the rounding of the
+    # fields themselves divided by w dt: about 2e-16 x ~20 (transform
+    # growth) x rms(F) / rms(dF).  The GPU's spectral increment has no such
+    # cancellation; the double bound of an increment is that oracle error.
+    incr = {"ddisp_x": "disp_x", "ddisp_y": "disp_y", "dh": "h"}
     for k in osurf.FACET_FIELDS:
         got = out[k].cpu().numpy().astype(np.float64)
         scale = np.sqrt(np.mean(ref[k] ** 2)) if k != "jac" else 1.0
         if scale == 0:
             scale = np.sqrt(np.mean(ref["h"] ** 2)) if k in ("disp_x", "disp_y") else \
                 np.sqrt(np.mean(ref["dh"] ** 2))
+        tol = 2e-5
+        if fp64:
+            tol = 1e-11
+            if k in incr and scale > 0:
+                base = np.sqrt(np.mean(ref[incr[k]] ** 2))
+                if base == 0:
+                    base = np.sqrt(np.mean(ref["h"] ** 2))
+                tol = max(tol, 5e-15 * base / scale)
         err = np.sqrt(np.mean((got - ref[k]) ** 2)) / scale
-        assert err <= tol, (k, err)
+        assert err <= tol, (k, err, tol)
     sim.close()
