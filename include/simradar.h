@@ -197,6 +197,25 @@ sim_status sim_range_doppler_accumulate(sim_ctx *ctx, const sim_grid *grid,
                                         sim_counters *counters,
                                         int32_t *facet_code, void *stream);
 
+/* sim_range_doppler_accumulate for callers that cannot allocate device memory
+ * or attach a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same results up to the
+ * summation order of the partial spectra; no workspace is needed, and the
+ * call allocates nothing: the band windows, their headers and the band
+ * counters live in a static device array of the library (32 MiB + 24 KiB per
+ * device, held until the process ends), which bounds the facet accumulate to
+ * 256 bands of 4 windows of at most 32 KiB.  Every supported size fits;
+ * anything beyond that bound returns SIM_ERR_WORKSPACE before launching.
+ * All calls of this entry point on one device share that array, so calls
+ * that overlap on one GPU (concurrent streams, several contexts or threads)
+ * race and must be serialised by the caller. */
+sim_status sim_range_doppler_accumulate_noalloc(sim_ctx *ctx, const sim_grid *grid,
+                                                const sim_facets *facets,
+                                                const sim_radar *radar, double t,
+                                                int32_t j, void *t_fast, int32_t n_spec,
+                                                sim_counters *counters,
+                                                int32_t *facet_code, void *stream);
+
 /* sim_surface_update followed by sim_range_doppler_accumulate for the pulse
  * pair (t, t + 1/PRF).  On the fused row path (SIM_TUNE_ROW_PATH) the facet
  * set is never written to memory; on the split path it goes through the

@@ -47,6 +47,21 @@ struct sim_ctx {
 __device__ __align__(256) float g_tw32[2 * simk::kTwEntries];
 __device__ __align__(256) double g_tw64[2 * simk::kTwEntries];
 
+// Scratch of sim_range_doppler_accumulate_noalloc: the band windows of
+// partial spectra (at most kNoAllocBands bands of kSlots windows of at most
+// 32 KiB: window_bins never makes one larger), then their headers and the
+// band counters.  One copy per device, held until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device (device_setup).  Nothing in it has to start at zero: a call
+// writes every header and counter it reads, and every window slot whose
+// header it marks valid.
+constexpr int kNoAllocBands = 256;
+constexpr size_t kNoAllocWinBytes = (size_t)kNoAllocBands * 4 * 32 * 1024;
+constexpr size_t kNoAllocHdrOff = kNoAllocWinBytes;
+constexpr size_t kNoAllocCntOff = kNoAllocHdrOff + (size_t)kNoAllocBands * 4 * 16;
+constexpr size_t kNoAllocBytes = kNoAllocCntOff + (size_t)kNoAllocBands * 8 * 4;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 using simk::kLdsBudget;
@@ -56,6 +71,9 @@ constexpr int kMaxBands = 512;       // bands (blocks) of the fused row pass
 constexpr int kAccBands = 512;       // bands (blocks) of the facet accumulate
 constexpr int kWsBands = kAccBands > kMaxBands ? kAccBands : kMaxBands;
 constexpr int kProfilePairs = 8192;  // timed launches per profile record
+static_assert(kNoAllocWinBytes == (size_t)kNoAllocBands * kSlots * kWindowBudget,
+              "scratch sized for the windows of kNoAllocBands bands");
+static_assert(kNoAllocBands <= kAccBands, "no more bands than the workspace path");
 
 bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(long v) {
@@ -165,6 +183,17 @@ WsLayout ws_layout(const sim_grid* g, const sim_radar* r, size_t cs) {
   return L;
 }
 
+// Facets per band and bands of the facet accumulate: the grid cut into at
+// most max_bands bands of at least 1024 facets.
+size_t acc_band_size(size_t P, int max_bands) {
+  size_t band = (P + max_bands - 1) / max_bands;
+  return band < 1024 ? 1024 : band;
+}
+int acc_band_count(size_t P, int max_bands) {
+  const size_t band = acc_band_size(P, max_bands);
+  return (int)((P + band - 1) / band);
+}
+
 void fill_grid(const sim_grid* g, GridP& gp) {
   gp.nx = g->nx;
   gp.ny = g->ny;
@@ -241,6 +270,7 @@ struct DeviceState {
   bool ready;
   void* tw32;
   void* tw64;
+  void* scratch;   // device address of `scratch` on this device
 };
 std::mutex g_dev_mutex;
 DeviceState g_dev[kMaxDevices];
@@ -266,14 +296,19 @@ sim_status device_setup(int device) {
   if (d.ready) return SIM_OK;
   void* a = nullptr;
   void* b = nullptr;
+  void* sc = nullptr;
   sim_status s = dev_err(hipGetSymbolAddress(&a, HIP_SYMBOL(g_tw32)), "twiddle table address");
   if (s == SIM_OK)
     s = dev_err(hipGetSymbolAddress(&b, HIP_SYMBOL(g_tw64)), "twiddle table address");
+  if (s == SIM_OK)
+    s = dev_err(hipGetSymbolAddress(&sc, HIP_SYMBOL(scratch)), "scratch address");
+  if (s == SIM_OK && (!a || !b || !sc)) s = dev_err(hipErrorInvalidSymbol, "static arrays");
   if (s == SIM_OK) s = fill_twiddles<float>(a);
   if (s == SIM_OK) s = fill_twiddles<double>(b);
   if (s != SIM_OK) return s;
   d.tw32 = a;
   d.tw64 = b;
+  d.scratch = sc;
   d.ready = true;
   return SIM_OK;
 }
@@ -287,10 +322,9 @@ bool facets_ok(const sim_facets* f) {
   return true;
 }
 
-WinP win_params(sim_ctx* c, const sim_radar* r, const WsLayout& L, int wk, int n_bands,
+WinP win_params(char* base, const sim_radar* r, const WsLayout& L, int wk, int n_bands,
                 int band_size) {
   WinP wp;
-  char* base = (char*)c->ws;
   wp.WK = wk;
   wp.log2WK = ilog2(wk);
   wp.S = kSlots;
@@ -379,7 +413,7 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, bo
     n_bands = 1;
     band_rows = rpl.rpb;
   }
-  const WinP wp = win_params(c, r, L, wk, n_bands, band_rows);
+  const WinP wp = win_params((char*)c->ws, r, L, wk, n_bands, band_rows);
   void* Tj = (char*)t_fast + (size_t)j * r->n_gates * r->n_doppler * cs;
   sim_status s;
   {
@@ -402,7 +436,8 @@ template <typename Real>
 sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
                              const sim_radar* r, double t, int32_t j, void* t_fast,
                              sim_counters* counters, int32_t* code, hipStream_t st,
-                             const WsLayout& L);
+                             const WsLayout& L, char* win_base = nullptr,
+                             int max_bands = kAccBands);
 
 // Row path of the fused call: the fused row pass (facets never leave the
 // chip), or the facet row pass into the workspace followed by the facet
@@ -444,11 +479,14 @@ sim_status accumulate_split(sim_ctx* c, const sim_grid* g, const void* spec0, bo
   return accumulate_facets<Real>(c, g, &f, r, t, j, t_fast, counters, code, st, L);
 }
 
+// Facet accumulate of update j.  The band windows, their headers and the
+// band counters are at the offsets of L from win_base (the context's
+// workspace when NULL); the facets are cut into at most max_bands bands.
 template <typename Real>
 sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
                              const sim_radar* r, double t, int32_t j, void* t_fast,
                              sim_counters* counters, int32_t* code, hipStream_t st,
-                             const WsLayout& L) {
+                             const WsLayout& L, char* win_base, int max_bands) {
   GridP gp;
   RadarP rp;
   fill_grid(g, gp);
@@ -457,10 +495,9 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
   const size_t P = (size_t)g->nx * g->ny;
-  size_t band = P / kAccBands;
-  if (band < 1024) band = 1024;
-  const int n_bands = (int)((P + band - 1) / band);
-  const WinP wp = win_params(c, r, L, wk, n_bands, (int)band);
+  const int n_bands = acc_band_count(P, max_bands);
+  const size_t band = acc_band_size(P, max_bands);
+  const WinP wp = win_params(win_base ? win_base : (char*)c->ws, r, L, wk, n_bands, (int)band);
   const size_t lds = (size_t)r->n_gates * wk * cs + simk::kWinCtxBytes;
   void* const fp[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
                        f->dh};
@@ -679,6 +716,44 @@ sim_status sim_range_doppler_accumulate(sim_ctx* ctx, const sim_grid* grid,
                                      st, L);
   return accumulate_facets<float>(ctx, grid, facets, radar, t, j, t_fast, counters, facet_code,
                                   st, L);
+}
+
+sim_status sim_range_doppler_accumulate_noalloc(sim_ctx* ctx, const sim_grid* grid,
+                                                const sim_facets* facets,
+                                                const sim_radar* radar, double t, int32_t j,
+                                                void* t_fast, int32_t n_spec,
+                                                sim_counters* counters, int32_t* facet_code,
+                                                void* stream) {
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!facets_ok(facets) || !t_fast || !isfin(t)) return SIM_ERR_ARG;
+  if (n_spec < 1 || j < 0 || j >= n_spec) return SIM_ERR_SHAPE;
+  const size_t cs = csize(ctx);
+  const int wk = window_bins(radar->n_gates, radar->n_doppler, cs, 0);
+  if (wk < 1) return SIM_ERR_UNSUPPORTED;
+  // the windows of this call must fit the scratch (every supported size does)
+  const int nb = acc_band_count((size_t)grid->nx * grid->ny, kNoAllocBands);
+  if (nb > kNoAllocBands ||
+      (size_t)nb * kSlots * radar->n_gates * (size_t)wk * cs > kNoAllocWinBytes)
+    return SIM_ERR_WORKSPACE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  char* base = (char*)g_dev[ctx->device].scratch;
+  if (!base) return SIM_ERR_DEVICE;
+  WsLayout L;
+  std::memset(&L, 0, sizeof(L));
+  L.part = 0;
+  L.hdr = kNoAllocHdrOff;
+  L.bandcnt = kNoAllocCntOff;
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->prec == SIM_PREC_FP64)
+    return accumulate_facets<double>(ctx, grid, facets, radar, t, j, t_fast, counters,
+                                     facet_code, st, L, base, kNoAllocBands);
+  return accumulate_facets<float>(ctx, grid, facets, radar, t, j, t_fast, counters, facet_code,
+                                  st, L, base, kNoAllocBands);
 }
 
 sim_status sim_update_and_accumulate(sim_ctx* ctx, const sim_grid* grid, const void* spec0,

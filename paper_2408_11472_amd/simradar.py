@@ -45,7 +45,7 @@ FACET_FIELDS = ("disp_x", "disp_y", "h", "sx", "sy", "jac",
 EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_get_precision", "sim_workspace_size", "sim_set_workspace",
             "sim_surface_update", "sim_range_doppler_accumulate",
-            "sim_update_and_accumulate", "sim_prepared_spectrum_size", "sim_prepare_spectrum",
+            "sim_range_doppler_accumulate_noalloc", "sim_update_and_accumulate", "sim_prepared_spectrum_size", "sim_prepare_spectrum",
             "sim_update_and_accumulate_prepared", "sim_segments_to_iq",
             "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
             "sim_range_doppler_accumulate_adjoint",
@@ -109,6 +109,10 @@ _sig = {
                                                     ctypes.POINTER(sim_facets),
                                                     ctypes.POINTER(sim_radar), _D, _I, _P,
                                                     _I, _P, _P, _P]),
+    "sim_range_doppler_accumulate_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid),
+                                                            ctypes.POINTER(sim_facets),
+                                                            ctypes.POINTER(sim_radar), _D, _I,
+                                                            _P, _I, _P, _P, _P]),
     "sim_update_and_accumulate": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P,
                                                  ctypes.POINTER(sim_radar), _D, _I, _P, _I,
                                                  _P, _P, _P]),
@@ -200,6 +204,16 @@ def sim_range_doppler_accumulate(ctx, grid, facets: sim_facets, radar, t, j, t_f
            _lib.sim_range_doppler_accumulate(ctx, ctypes.byref(grid), ctypes.byref(facets),
                                              ctypes.byref(radar), t, j, t_fast_ptr, n_spec,
                                              counters_ptr, code_ptr, stream))
+
+
+def sim_range_doppler_accumulate_noalloc(ctx, grid, facets: sim_facets, radar, t, j,
+                                         t_fast_ptr, n_spec, counters_ptr, code_ptr,
+                                         stream) -> None:
+    _check("sim_range_doppler_accumulate_noalloc",
+           _lib.sim_range_doppler_accumulate_noalloc(ctx, ctypes.byref(grid),
+                                                     ctypes.byref(facets), ctypes.byref(radar),
+                                                     t, j, t_fast_ptr, n_spec, counters_ptr,
+                                                     code_ptr, stream))
 
 
 def sim_update_and_accumulate(ctx, grid, spec0_ptr, radar, t, j, t_fast_ptr, n_spec,
@@ -407,6 +421,23 @@ class Simulator:
         r = self.radar
         g = self.grid
         sim_range_doppler_accumulate(
+            self.ctx, self.grid, self._facets_struct(facets), self.radar, float(t), int(j),
+            self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
+            n_spec,
+            None if counters is None else self._need(counters, self.torch.int64, (6,), "counters"),
+            None if facet_code is None else self._need(facet_code, self.torch.int32,
+                                                       (g.ny, g.nx), "facet_code"),
+            self._stream(stream))
+
+    def range_doppler_accumulate_noalloc(self, facets, t, j, t_fast, counters=None,
+                                         facet_code=None, stream=None):
+        """range_doppler_accumulate through the entry point that uses the
+        library's static scratch instead of the workspace (allocates
+        nothing)."""
+        n_spec = t_fast.shape[0]
+        r = self.radar
+        g = self.grid
+        sim_range_doppler_accumulate_noalloc(
             self.ctx, self.grid, self._facets_struct(facets), self.radar, float(t), int(j),
             self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
             n_spec,
