@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 3
+#define SIM_ABI_VERSION 4
 
 typedef enum sim_status {
   SIM_OK = 0,
@@ -301,6 +301,78 @@ sim_status sim_range_doppler_accumulate_adjoint(sim_ctx *ctx, const sim_grid *gr
                                                 void *grad_h, void *grad_sx, void *grad_sy,
                                                 void *stream);
 
+/* ---- look-up tables of the facet amplitude ---------------------------------
+ * Sec. II.A: the antenna patterns of a simulation are recorded on a u-v grid
+ * and interpolated at each facet, and the NRCS comes from look-up tables over
+ * the local scattering geometry.  With tables set, the accumulate calls of
+ * the context use
+ *   a = sqrt(sigma0(theta_l) A) ant(u, v) (H / R)^2       (complex)
+ * where (u, v) = ((P_x - S_x) / R, (P_y - S_y) / R) are the direction
+ * cosines of the line of sight, ant is interpolated bilinearly on the grid
+ * u = u0 + iu du, v = v0 + iv dv of the [nv][nu] complex table (the last node
+ * belonging to the cell before it, zero outside the grid), theta_l is the
+ * local incidence (tan^2 theta_l = |d x m|^2 / (d . m)^2 of the closed form)
+ * and sigma0 is interpolated linearly in the [n_theta] real table over
+ * theta_l = i dtheta (zero beyond).  A NULL table keeps its closed form
+ * (Gaussian two-way beam, geometric-optics NRCS).  The arrays are caller-owned
+ * device memory in the context precision and must stay valid while the
+ * context uses them.  The adjoint call rejects a context with tables
+ * (SIM_ERR_UNSUPPORTED). */
+typedef struct sim_tables {
+  const void *antenna;      /* [nv][nu] complex, or NULL                 */
+  int32_t nu, nv;           /* >= 2 each                                 */
+  double u0, du, v0, dv;    /* grid origin and spacing (du, dv > 0)      */
+  const void *nrcs;         /* [n_theta] real, or NULL                   */
+  int32_t n_theta;          /* >= 2                                      */
+  int32_t reserved;
+  double dtheta;            /* [rad] > 0                                 */
+} sim_tables;
+
+/* Set (or, with NULL or two NULL tables, clear) the context's tables.  The
+ * call waits for the device to be idle, then writes the table parameters to
+ * a per-context block of the library's static device memory (256 contexts
+ * with tables per device; SIM_ERR_UNSUPPORTED beyond). */
+sim_status sim_set_tables(sim_ctx *ctx, const sim_tables *tables);
+
+/* ---- Delay-Doppler processing --------------------------------------------
+ * Focusing of the simulated IQ as in Sec. IV.C: the pulses are cut into
+ * bursts of M, and for each burst b
+ *   1. the Doppler centroid u_c (cycles per pulse) is removed:
+ *      y'[x][g] = y[b M + x][g] exp(-2 pi i u_c x); u_c is given, or
+ *      estimated per burst as arg(sum_{x,g} y[x+1][g] conj y[x][g]) / (2 pi);
+ *   2. an along-track DFT forms M Doppler beams:
+ *      Z[b][f][g] = sum_x y'[x][g] exp(-2 pi i f x / M) (beam f at f_s / M
+ *      cycles per pulse, f_s = f or f - M);
+ *   3. with migration != 0, the range migration of each beam is undone:
+ *      Z[b][f][.] <- IDFT(DFT(Z[b][f][.]) exp(+2 pi i q delta_f / G)) / G over
+ *      the gates (q in FFT order), delta_f = dy^2 / (2 H dr) gates for the
+ *      along-track offset dy = (f_s / M) PRF lambda H / (2 v) of the beam;
+ * then the beam powers are multi-looked: beam_power[f][g] = mean_b
+ * |Z[b][f][g]|^2 and waveform[g] = mean_f beam_power[f][g].  Trailing pulses
+ * that do not fill a burst are ignored.  The IQ convention is that of
+ * sim_segments_to_iq (a scatterer of Doppler u has y[x] ~ exp(+2 pi i u x)).
+ * Sizes: M a power of two in [2, 256]; n_gates a power of two in [2, 2048];
+ * at least one burst.  Reals and complexes follow the context precision. */
+#define SIM_DD_CENTROID_GIVEN 0
+#define SIM_DD_CENTROID_ESTIMATE 1
+typedef struct sim_dd_params {
+  int32_t burst;            /* M, pulses per burst                        */
+  int32_t centroid_mode;    /* SIM_DD_CENTROID_*                          */
+  double centroid;          /* u_c [cycles per pulse] when given          */
+  int32_t migration;        /* != 0: step 3                               */
+  int32_t reserved;
+} sim_dd_params;
+
+/*   y           [n_pulses][n_gates] complex, read only.
+ *   beams       [n_pulses / M][M][n_gates] complex, written (focused beams).
+ *   centroid    [n_pulses / M] real, written (the centroid used per burst).
+ *   beam_power  [M][n_gates] real, written.
+ *   waveform    [n_gates] real, written.
+ * radar->velocity must be nonzero when migration != 0. */
+sim_status sim_delay_doppler(sim_ctx *ctx, const sim_radar *radar, const void *y,
+                             int32_t n_pulses, const sim_dd_params *params, void *beams,
+                             void *centroid, void *beam_power, void *waveform, void *stream);
+
 /* ---- batches of independent realisations --------------------------------
  * The paper averages spectra over ~100 realisations of the acquisition
  * (Sec. I, Sec. IV.D).  A batch holds R realisations with their own grid
@@ -329,6 +401,67 @@ sim_status sim_batch_workspace_size(const sim_batch *batch, size_t *bytes);
 sim_status sim_batch_run(sim_batch *batch, void *const *spec0, void *const *t_fast,
                          void *const *y, int use_graph, void *stream);
 
+/* How a batch runs its updates:
+ *   SIM_BATCH_LANES       every member on its own, members dealt over four
+ *                         streams that overlap the launches of small grids;
+ *   SIM_BATCH_PERSISTENT  per update and per shape (members with the same
+ *                         grid sides, gates and bins), each phase of the
+ *                         update (column pass, facet row pass, facet
+ *                         accumulate, ordered reduce) is one persistent
+ *                         launch over all members of the shape: a grid of as
+ *                         many blocks as the GPU holds takes (member, block)
+ *                         work items from a device counter until none is left.
+ * Both give the results of the single-member calls (up to summation order).
+ * The default is SIM_BATCH_PERSISTENT; the batch workspace covers both. */
+#define SIM_BATCH_LANES 1
+#define SIM_BATCH_PERSISTENT 2
+sim_status sim_batch_set_mode(sim_batch *batch, int mode);
+
+/* Per-member tuning of the lanes mode (SIM_TUNE_ROW_PATH or
+ * SIM_TUNE_ROW_BANDS, as sim_set_tuning): an autotuner sets each member the
+ * values it found for that member's shape.  Members without their own value
+ * use the context's.  The persistent mode always runs the split row path.
+ * A graph captured by the batch is dropped (the next graph run captures
+ * again with the new values). */
+sim_status sim_batch_set_tuning(sim_batch *batch, int32_t member, int key, int value);
+
+/* ---- out-of-core runs -------------------------------------------------------
+ * Sec. III.B keeps the main tensors in host memory and only caches on the
+ * GPU.  A streamer runs Algorithm 1 and the post-processing for a whole run
+ * with T_fast and Y in host memory: the device holds two cache buffers of
+ * K + 1 spectra and K n_fast pulses (K = chunk_updates); chunk after chunk,
+ * the spectra of K update intervals are computed into one buffer (the first
+ * spectrum of a chunk is the last of the previous one, copied on the device),
+ * the chunk's IQ is formed from them on the device, and a copy stream of the
+ * streamer moves the IQ (and the spectra) to host memory while the next chunk
+ * is computed into the other buffer.  Results equal sim_update_and_accumulate
+ * over every spectrum followed by sim_segments_to_iq (up to the summation
+ * order of the partial spectra).  The host buffers should be pinned
+ * (hipHostMalloc) for the copies to overlap the computation. */
+typedef struct sim_streamer sim_streamer;
+
+/* Streamer for runs of `radar` on the context's device (makes its copy
+ * stream and events). */
+sim_status sim_streamer_create(sim_ctx *ctx, const sim_radar *radar, int32_t chunk_updates,
+                               sim_streamer **streamer);
+sim_status sim_streamer_destroy(sim_streamer *streamer);
+
+/* Device cache bytes sim_streamer_run needs (two buffers). */
+sim_status sim_streamer_cache_size(const sim_streamer *streamer, size_t *bytes);
+
+/* One run of n_updates update intervals on `stream`:
+ *   prepared     the spectrum in the column-pass layout (sim_prepare_spectrum).
+ *   t_fast_host  [n_updates + 1][G][N] complex host memory, written; may be NULL.
+ *   y_host       [n_updates n_fast][G] complex host memory, written.
+ *   cache        device memory of >= sim_streamer_cache_size bytes, 256-byte
+ *                aligned.
+ * The context's workspace serves the surface transform as in
+ * sim_update_and_accumulate.  When `stream` completes, the host buffers hold
+ * the results. */
+sim_status sim_streamer_run(sim_streamer *streamer, const sim_grid *grid, const void *prepared,
+                            int32_t n_updates, void *t_fast_host, void *y_host, void *cache,
+                            size_t cache_bytes, void *stream);
+
 /* ---- tuning ---------------------------------------------------------------
  * Launch parameters that do not change results beyond summation order;
  * bench/autotune code sets them per context. */
@@ -354,7 +487,9 @@ sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 #define SIM_KERNEL_SEGMENTS_TO_IQ 5       /* T_fast -> Y                         */
 #define SIM_KERNEL_ADJOINT 6              /* waveform loss and adjoint kernels   */
 #define SIM_KERNEL_PREPARE 7              /* spectrum preparation, batch clears  */
-#define SIM_KERNEL_KINDS 8
+#define SIM_KERNEL_DELAY_DOPPLER 8        /* Delay-Doppler processing of the IQ  */
+#define SIM_KERNEL_BATCHED_UPDATE 9       /* persistent batched update (4 launches) */
+#define SIM_KERNEL_KINDS 10
 
 typedef struct sim_kernel_times {
   double ms[SIM_KERNEL_KINDS];

@@ -90,3 +90,48 @@ def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
         cache[key] = entry
         _store(cache)
     return entry
+
+
+def tune_batch(batch, specs, T, Y=None, repeats: int = 2, shapes: bool = True) -> dict:
+    """Pick the batch mode (lanes or persistent launches) by timing replays of
+    the captured graph of each, and, with shapes=True, tune the row path of
+    every member shape first (lanes mode runs each member through the
+    context's row path; the persistent launches use the split path).
+    Returns {"mode": ..., "times_ms": {...}, "shapes": {...}}."""
+    import time
+
+    import torch
+    from . import simradar
+    out = {"shapes": {}}
+    if shapes:
+        seen = {}
+        for g, r, s in zip(batch.grids, batch.radars, specs):
+            key = (g.nx, g.ny, r.n_gates, r.n_doppler)
+            if key in seen:
+                continue
+            sim = simradar.Simulator(g, r, batch.precision, device=batch.device.index or 0)
+            seen[key] = tune(sim, s)
+            sim.close()
+        out["shapes"] = {f"{k[0]}x{k[1]}_G{k[2]}_N{k[3]}": v for k, v in seen.items()}
+        # every member runs (in the lanes mode) with its shape's values
+        for i, (g, r) in enumerate(zip(batch.grids, batch.radars)):
+            e = seen[(g.nx, g.ny, r.n_gates, r.n_doppler)]
+            simradar.sim_batch_set_tuning(batch.batch, i, simradar.SIM_TUNE_ROW_PATH,
+                                          e["row_path"])
+            simradar.sim_batch_set_tuning(batch.batch, i, simradar.SIM_TUNE_ROW_BANDS,
+                                          e["row_bands"])
+    times = {}
+    for name, mode in (("lanes", simradar.SIM_BATCH_LANES),
+                       ("persistent", simradar.SIM_BATCH_PERSISTENT)):
+        batch.set_mode(mode)
+        batch.run(specs, T, Y, use_graph=True)            # capture + warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            batch.run(specs, T, Y, use_graph=True)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / repeats * 1e3
+    best = min(times, key=times.get)
+    batch.set_mode(simradar.SIM_BATCH_LANES if best == "lanes" else simradar.SIM_BATCH_PERSISTENT)
+    out.update({"mode": best, "times_ms": {k: round(v, 3) for k, v in times.items()}})
+    return out

@@ -37,6 +37,7 @@ struct sim_ctx {
   std::vector<int> kind;        // kernel kind of each recorded pair
   size_t used;                  // pairs recorded
   uint64_t dropped;             // launches not timed (pool exhausted)
+  int tab_slot;                 // slot of the look-up tables (-1: closed forms)
 };
 
 // Twiddle tables (entries [M, 2M) hold e^{+2 pi i m / M} for every power of
@@ -61,6 +62,12 @@ constexpr size_t kNoAllocHdrOff = kNoAllocWinBytes;
 constexpr size_t kNoAllocCntOff = kNoAllocHdrOff + (size_t)kNoAllocBands * 4 * 16;
 constexpr size_t kNoAllocBytes = kNoAllocCntOff + (size_t)kNoAllocBands * 8 * 4;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Parameter blocks of the look-up tables (sim_set_tables), one slot per
+// context that has tables, per device; the kernels read the block through
+// its device address.
+constexpr int kTabSlots = 256;
+__device__ __align__(256) simk::TabP g_tab_slots[kTabSlots];
 
 namespace {
 
@@ -211,7 +218,9 @@ void fill_grid(const sim_grid* g, GridP& gp) {
 // Platform positions, Doppler constant and amplitude constants.  The double
 // expressions below are the ones the range and index arithmetic is defined
 // with (evaluated once here, in this order).
-void fill_radar(const sim_radar* r, const sim_grid* g, double t, RadarP& rp) {
+void fill_radar(const sim_radar* r, const sim_grid* g, double t, RadarP& rp,
+                const simk::TabP* tab = nullptr) {
+  rp.tab = tab;
   rp.altitude = r->altitude;
   rp.sat_x = r->sat_x;
   rp.sat_y1 = r->sat_y0 + r->velocity * t;
@@ -271,6 +280,8 @@ struct DeviceState {
   void* tw32;
   void* tw64;
   void* scratch;   // device address of `scratch` on this device
+  simk::TabP* tabs;              // device address of g_tab_slots
+  bool tab_used[kTabSlots];      // slots held by live contexts
 };
 std::mutex g_dev_mutex;
 DeviceState g_dev[kMaxDevices];
@@ -302,15 +313,33 @@ sim_status device_setup(int device) {
     s = dev_err(hipGetSymbolAddress(&b, HIP_SYMBOL(g_tw64)), "twiddle table address");
   if (s == SIM_OK)
     s = dev_err(hipGetSymbolAddress(&sc, HIP_SYMBOL(scratch)), "scratch address");
-  if (s == SIM_OK && (!a || !b || !sc)) s = dev_err(hipErrorInvalidSymbol, "static arrays");
+  void* tb = nullptr;
+  if (s == SIM_OK)
+    s = dev_err(hipGetSymbolAddress(&tb, HIP_SYMBOL(g_tab_slots)), "table slots address");
+  if (s == SIM_OK && (!a || !b || !sc || !tb))
+    s = dev_err(hipErrorInvalidSymbol, "static arrays");
   if (s == SIM_OK) s = fill_twiddles<float>(a);
   if (s == SIM_OK) s = fill_twiddles<double>(b);
   if (s != SIM_OK) return s;
   d.tw32 = a;
   d.tw64 = b;
   d.scratch = sc;
+  d.tabs = (simk::TabP*)tb;
+  for (bool& u : d.tab_used) u = false;
   d.ready = true;
   return SIM_OK;
+}
+
+// Device address of the context's table parameter block, or null.
+const simk::TabP* ctx_tab(const sim_ctx* c) {
+  return c->tab_slot >= 0 ? g_dev[c->device].tabs + c->tab_slot : nullptr;
+}
+
+void release_tab_slot(sim_ctx* c) {
+  if (c->tab_slot < 0) return;
+  std::lock_guard<std::mutex> lock(g_dev_mutex);
+  g_dev[c->device].tab_used[c->tab_slot] = false;
+  c->tab_slot = -1;
 }
 
 bool facets_ok(const sim_facets* f) {
@@ -390,7 +419,7 @@ sim_status accumulate_fused(sim_ctx* c, const sim_grid* g, const void* spec0, bo
   GridP gp;
   RadarP rp;
   fill_grid(g, gp);
-  fill_radar(r, g, t, rp);
+  fill_radar(r, g, t, rp, ctx_tab(c));
   const size_t cs = sizeof(Real) * 2;
   char* base = (char*)c->ws;
   void* planes = base + L.planes;
@@ -490,7 +519,7 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
   GridP gp;
   RadarP rp;
   fill_grid(g, gp);
-  fill_radar(r, g, t, rp);
+  fill_radar(r, g, t, rp, ctx_tab(c));
   const size_t cs = sizeof(Real) * 2;
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
@@ -564,12 +593,14 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->row_bands = 0;
   c->row_path = SIM_ROW_PATH_AUTO;
   c->capturing = false;
+  c->tab_slot = -1;
   *ctx = c;
   return SIM_OK;
 }
 
 sim_status sim_destroy(sim_ctx* ctx) {
   if (!ctx) return SIM_OK;
+  release_tab_slot(ctx);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
   return SIM_OK;
@@ -868,6 +899,7 @@ sim_status sim_range_doppler_accumulate_adjoint(sim_ctx* ctx, const sim_grid* gr
                                                 const void* t_fast_bar, int32_t n_spec,
                                                 void* grad_h, void* grad_sx, void* grad_sy,
                                                 void* stream) {
+  if (ctx && ctx->tab_slot >= 0) return SIM_ERR_UNSUPPORTED;   // closed forms only
   if (!ctx) return SIM_ERR_ARG;
   sim_status s = check_grid(ctx, grid);
   if (s != SIM_OK) return s;
@@ -892,6 +924,85 @@ sim_status sim_range_doppler_accumulate_adjoint(sim_ctx* ctx, const sim_grid* gr
     return dev(simk::launch_accumulate_adjoint<double>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy,
                                                        st));
   return dev(simk::launch_accumulate_adjoint<float>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy, st));
+}
+
+sim_status sim_delay_doppler(sim_ctx* ctx, const sim_radar* radar, const void* y,
+                             int32_t n_pulses, const sim_dd_params* params, void* beams,
+                             void* centroid, void* beam_power, void* waveform, void* stream) {
+  if (!ctx || !params) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  const int M = params->burst, G = radar->n_gates;
+  if (!is_pow2(M) || M < 2 || M > 256 || !is_pow2(G) || G < 2 || G > 2048)
+    return SIM_ERR_UNSUPPORTED;
+  if (n_pulses < M) return SIM_ERR_SHAPE;
+  if (params->centroid_mode != SIM_DD_CENTROID_GIVEN &&
+      params->centroid_mode != SIM_DD_CENTROID_ESTIMATE)
+    return SIM_ERR_ARG;
+  if (!isfin(params->centroid)) return SIM_ERR_ARG;
+  if (params->migration && radar->velocity == 0.0) return SIM_ERR_ARG;
+  if (!y || !beams || !centroid || !beam_power || !waveform) return SIM_ERR_ARG;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  const int nb = n_pulses / M;
+  // range migration per squared beam Doppler (cycles per pulse), in gates
+  double mig = 0.0;
+  if (params->migration) {
+    const double lam = 299792458.0 / radar->carrier_hz;
+    const double a = radar->prf_hz * lam * radar->altitude / (2.0 * radar->velocity);
+    mig = a * a / (2.0 * radar->altitude * radar->gate_spacing);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope p(ctx, SIM_KERNEL_DELAY_DOPPLER, st);
+  if (ctx->prec == SIM_PREC_FP64)
+    return dev(simk::launch_delay_doppler<double>(
+        y, G, M, nb, params->centroid_mode, params->centroid, mig, params->migration, beams,
+        centroid, beam_power, waveform, ctx->tw, st));
+  return dev(simk::launch_delay_doppler<float>(
+      y, G, M, nb, params->centroid_mode, params->centroid, mig, params->migration, beams,
+      centroid, beam_power, waveform, ctx->tw, st));
+}
+
+sim_status sim_set_tables(sim_ctx* ctx, const sim_tables* t) {
+  if (!ctx) return SIM_ERR_ARG;
+  if (!t || (!t->antenna && !t->nrcs)) {
+    release_tab_slot(ctx);
+    return SIM_OK;
+  }
+  if (t->antenna && !(t->nu >= 2 && t->nv >= 2 && isfin(t->u0) && isfin(t->v0) &&
+                      isfin(t->du) && t->du > 0 && isfin(t->dv) && t->dv > 0))
+    return SIM_ERR_ARG;
+  if (t->nrcs && !(t->n_theta >= 2 && isfin(t->dtheta) && t->dtheta > 0)) return SIM_ERR_ARG;
+  sim_status s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  DeviceState& d = g_dev[ctx->device];
+  if (ctx->tab_slot < 0) {
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    for (int i = 0; i < kTabSlots; ++i) {
+      if (!d.tab_used[i]) {
+        d.tab_used[i] = true;
+        ctx->tab_slot = i;
+        break;
+      }
+    }
+    if (ctx->tab_slot < 0) return SIM_ERR_UNSUPPORTED;
+  }
+  simk::TabP p;
+  std::memset(&p, 0, sizeof(p));
+  p.ant = t->antenna;
+  p.nrcs = t->nrcs;
+  p.nu = t->antenna ? t->nu : 0;
+  p.nv = t->antenna ? t->nv : 0;
+  p.n_theta = t->nrcs ? t->n_theta : 0;
+  p.u0 = t->u0;
+  p.v0 = t->v0;
+  p.inv_du = t->antenna ? 1.0 / t->du : 0.0;
+  p.inv_dv = t->antenna ? 1.0 / t->dv : 0.0;
+  p.inv_dtheta = t->nrcs ? 1.0 / t->dtheta : 0.0;
+  // no kernel of this device may read the block while it changes
+  s = dev(hipDeviceSynchronize());
+  if (s != SIM_OK) return s;
+  return dev(hipMemcpy(d.tabs + ctx->tab_slot, &p, sizeof(p), hipMemcpyHostToDevice));
 }
 
 sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
@@ -983,9 +1094,135 @@ struct sim_batch {
   bool have_graph;
   std::vector<void*> key;
   hipStream_t graph_stream;
+  // persistent mode: members grouped by shape (grid sides, gates, bins);
+  // each member's workspace slice; the per-update descriptors of every
+  // class and the work counters of every launch in the workspace
+  int mode;                                   // SIM_BATCH_*
+  std::vector<std::vector<int>> classes;      // member indices per class
+  std::vector<size_t> member_off;             // workspace slice of each member
+  size_t desc_off, queue_off;
+  std::vector<simk::BatchMember> desc;        // host copy, [update][member of class order]
+  std::vector<size_t> desc_at;                // first descriptor of (update, class)
+  std::vector<int> desc_n;                    // active members of (update, class)
+  std::vector<void*> desc_key;                // pointers the descriptors were built for
+  int jmax;
+  std::vector<int> m_row_path, m_row_bands;   // per-member tuning (lanes mode)
 };
 
 namespace {
+
+template <typename Real>
+void build_descriptors(sim_batch* b, void* const* t_fast) {
+  sim_ctx* c = b->ctx;
+  const size_t cs = sizeof(Real) * 2;
+  const int nc = (int)b->classes.size();
+  b->desc.clear();
+  b->desc_at.assign((size_t)(b->jmax + 1) * nc, 0);
+  b->desc_n.assign((size_t)(b->jmax + 1) * nc, 0);
+  for (int j = 0; j <= b->jmax; ++j) {
+    for (int k = 0; k < nc; ++k) {
+      b->desc_at[(size_t)j * nc + k] = b->desc.size();
+      for (int r : b->classes[k]) {
+        if (j > b->updates[r]) continue;
+        const sim_grid* g = &b->grids[r];
+        const sim_radar* rr = &b->radars[r];
+        const WsLayout L = ws_layout(g, rr, cs);
+        char* base = (char*)c->ws + b->member_off[r];
+        const double t = ((double)j * rr->n_fast) / rr->prf_hz;
+        simk::BatchMember m;
+        std::memset(&m, 0, sizeof(m));
+        GridP gp;
+        fill_grid(g, gp);
+        m.gp = simk::grid_with_tiles<Real>(gp);
+        fill_radar(rr, g, t, m.rp, ctx_tab(c));
+        const size_t P = (size_t)g->nx * g->ny;
+        const int wk = window_bins(rr->n_gates, rr->n_doppler, cs, 0);
+        m.wp = win_params(base, rr, L, wk, acc_band_count(P, kAccBands),
+                          (int)acc_band_size(P, kAccBands));
+        m.spec = (char*)c->ws + b->prep_off[r];
+        m.planes = base + L.planes;
+        for (int i = 0; i < 9; ++i) m.fac[i] = base + L.facets + (size_t)i * L.facet_stride;
+        m.Tj = (char*)t_fast[r] + (size_t)j * rr->n_gates * rr->n_doppler * cs;
+        m.t = t;
+        m.dt = 1.0 / rr->prf_hz;
+        b->desc.push_back(m);
+        b->desc_n[(size_t)j * nc + k]++;
+      }
+    }
+  }
+}
+
+// Persistent mode: every update j runs, per class, the four phases of the
+// split row path as four persistent launches over all members of the class.
+template <typename Real>
+sim_status persistent_updates(sim_batch* b, hipStream_t st) {
+  sim_ctx* c = b->ctx;
+  const size_t cs = sizeof(Real) * 2;
+  const int nc = (int)b->classes.size();
+  const simk::BatchMember* dev_desc = (const simk::BatchMember*)((char*)c->ws + b->desc_off);
+  int* queues = (int*)((char*)c->ws + b->queue_off);
+  sim_status s = dev(simk::launch_clear(queues, (size_t)(b->jmax + 1) * nc * 4 * sizeof(int), st));
+  for (int j = 0; j <= b->jmax && s == SIM_OK; ++j) {
+    for (int k = 0; k < nc && s == SIM_OK; ++k) {
+      const size_t at = b->desc_at[(size_t)j * nc + k];
+      const int n = b->desc_n[(size_t)j * nc + k];
+      if (n == 0) continue;
+      const simk::BatchMember& m0 = b->desc[at];
+      const int r0 = b->classes[k][0];
+      const int wk = window_bins(b->radars[r0].n_gates, b->radars[r0].n_doppler, cs, 0);
+      const size_t acc_lds = (size_t)b->radars[r0].n_gates * wk * cs + simk::kWinCtxBytes;
+      ProfScope p(c, SIM_KERNEL_BATCHED_UPDATE, st);
+      s = dev(simk::launch_update_batched<Real>(dev_desc + at, n, m0.gp, m0.rp, m0.wp, acc_lds,
+                                                queues + 4 * ((size_t)j * nc + k), c->tw, st));
+    }
+  }
+  return s;
+}
+
+sim_status batch_enqueue_persistent(sim_batch* b, void* const* spec0, void* const* t_fast,
+                                    void* const* y, hipStream_t st) {
+  sim_ctx* c = b->ctx;
+  const int R = (int)b->grids.size();
+  const size_t cs = csize(c);
+  for (int r = 0; r < R; ++r) {
+    const sim_radar& rr = b->radars[r];
+    const size_t n = (size_t)(b->updates[r] + 1) * rr.n_gates * rr.n_doppler;
+    ProfScope p(c, SIM_KERNEL_PREPARE, st);
+    const sim_status s = dev(simk::launch_clear(t_fast[r], n * cs, st));
+    if (s != SIM_OK) return s;
+  }
+  for (int r = 0; r < R; ++r) {
+    const sim_status s = sim_prepare_spectrum(c, &b->grids[r], spec0[r],
+                                              (char*)c->ws + b->prep_off[r], st);
+    if (s != SIM_OK) return s;
+  }
+  sim_status s = c->prec == SIM_PREC_FP64 ? persistent_updates<double>(b, st)
+                                          : persistent_updates<float>(b, st);
+  for (int r = 0; r < R && s == SIM_OK && y; ++r) {
+    if (!y[r]) continue;
+    s = sim_segments_to_iq(c, &b->radars[r], t_fast[r], b->updates[r] + 1, y[r], st);
+  }
+  return s;
+}
+
+// The descriptors depend on the output pointers: rebuilt and uploaded when
+// they change (after the stream has drained, so that no queued launch still
+// reads the old ones).
+sim_status batch_prepare_descriptors(sim_batch* b, void* const* t_fast, hipStream_t st) {
+  std::vector<void*> key(t_fast, t_fast + b->grids.size());
+  key.push_back(b->ctx->ws);
+  if (key == b->desc_key && !b->desc.empty()) return SIM_OK;
+  if (b->ctx->prec == SIM_PREC_FP64)
+    build_descriptors<double>(b, t_fast);
+  else
+    build_descriptors<float>(b, t_fast);
+  sim_status s = dev(hipStreamSynchronize(st));
+  if (s != SIM_OK) return s;
+  s = dev(hipMemcpy((char*)b->ctx->ws + b->desc_off, b->desc.data(),
+                    b->desc.size() * sizeof(simk::BatchMember), hipMemcpyHostToDevice));
+  if (s == SIM_OK) b->desc_key = key;
+  return s;
+}
 
 sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, void* const* y,
                          hipStream_t st) {
@@ -1028,6 +1265,7 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
     lc.row_bands = c->row_bands;
     lc.row_path = c->row_path;
     lc.capturing = c->capturing;
+    lc.tab_slot = c->tab_slot;
     lc.profiling = false;
     lc.used = 0;
     lc.dropped = 0;
@@ -1037,6 +1275,8 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
         if (b->lane_of[r] != l || j > b->updates[r]) continue;
         const sim_radar& rr = b->radars[r];
         const double t = ((double)j * rr.n_fast) / rr.prf_hz;
+        lc.row_path = b->m_row_path[r] >= 0 ? b->m_row_path[r] : c->row_path;
+        lc.row_bands = b->m_row_bands[r] >= 0 ? b->m_row_bands[r] : c->row_bands;
         first = sim_update_and_accumulate_prepared(
             &lc, &b->grids[r], (char*)c->ws + b->prep_off[r], &rr, t, j, t_fast[r],
             b->updates[r] + 1, nullptr, nullptr, ls);
@@ -1120,6 +1360,42 @@ sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
     b->prep_off.push_back(off);
     off = align256(off + pb);
   }
+  // persistent mode: one workspace slice per member (the lanes' slices and
+  // these are never in use together), then the descriptors and counters
+  b->mode = SIM_BATCH_PERSISTENT;
+  b->m_row_path.assign(n_real, -1);
+  b->m_row_bands.assign(n_real, -1);
+  b->jmax = 0;
+  for (int r = 0; r < n_real; ++r) b->jmax = n_updates[r] > b->jmax ? n_updates[r] : b->jmax;
+  for (int r = 0; r < n_real; ++r) {
+    bool placed = false;
+    for (auto& cl : b->classes) {
+      const int q = cl[0];
+      if (grids[q].nx == grids[r].nx && grids[q].ny == grids[r].ny &&
+          radars[q].n_gates == radars[r].n_gates && radars[q].n_doppler == radars[r].n_doppler) {
+        cl.push_back(r);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) b->classes.push_back(std::vector<int>(1, r));
+  }
+  size_t poff = 0;
+  for (int r = 0; r < n_real; ++r) {
+    b->member_off.push_back(poff);
+    poff = align256(poff + ws_layout(&grids[r], &radars[r], csize(ctx)).total);
+  }
+  // both modes start at offset 0: the prepared spectra move past the larger
+  const size_t lanes_end = b->lane_off.empty() ? 0 : b->prep_off[0];
+  if (poff > lanes_end) {
+    const size_t shift = poff - lanes_end;
+    for (size_t& o : b->prep_off) o += shift;
+    off += shift;
+  }
+  b->desc_off = off;
+  off = align256(off + (size_t)(b->jmax + 1) * n_real * sizeof(simk::BatchMember));
+  b->queue_off = off;
+  off = align256(off + (size_t)(b->jmax + 1) * b->classes.size() * 4 * sizeof(int));
   b->ws_bytes = off;
   bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
   for (int l = 0; l < NL && ok; ++l) {
@@ -1157,6 +1433,34 @@ sim_status sim_batch_destroy(sim_batch* b) {
   return s;
 }
 
+sim_status sim_batch_set_mode(sim_batch* b, int mode) {
+  if (!b) return SIM_ERR_ARG;
+  if (mode != SIM_BATCH_LANES && mode != SIM_BATCH_PERSISTENT) return SIM_ERR_ARG;
+  b->mode = mode;
+  return SIM_OK;
+}
+
+sim_status sim_batch_set_tuning(sim_batch* b, int32_t member, int key, int value) {
+  if (!b || member < 0 || member >= (int)b->grids.size()) return SIM_ERR_ARG;
+  // a captured graph holds the launches of the old values
+  if (b->have_graph) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->have_graph = false;
+  }
+  if (key == SIM_TUNE_ROW_PATH) {
+    if (value != SIM_ROW_PATH_AUTO && value != SIM_ROW_PATH_FUSED && value != SIM_ROW_PATH_SPLIT)
+      return SIM_ERR_ARG;
+    b->m_row_path[member] = value;
+    return SIM_OK;
+  }
+  if (key == SIM_TUNE_ROW_BANDS) {
+    if (value < 0 || value > kMaxBands || (value > 0 && !is_pow2(value))) return SIM_ERR_ARG;
+    b->m_row_bands[member] = value;
+    return SIM_OK;
+  }
+  return SIM_ERR_ARG;
+}
+
 sim_status sim_batch_workspace_size(const sim_batch* b, size_t* bytes) {
   if (!b || !bytes) return SIM_ERR_ARG;
   *bytes = b->ws_bytes;
@@ -1175,10 +1479,20 @@ sim_status sim_batch_run(sim_batch* b, void* const* spec0, void* const* t_fast, 
   sim_status s = use_device(c);
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  if (!use_graph) return batch_enqueue(b, spec0, t_fast, y, st);
+  const bool pers = b->mode == SIM_BATCH_PERSISTENT;
+  if (pers) {
+    s = batch_prepare_descriptors(b, t_fast, st);
+    if (s != SIM_OK) return s;
+  }
+  auto enqueue = [&]() {
+    return pers ? batch_enqueue_persistent(b, spec0, t_fast, y, st)
+                : batch_enqueue(b, spec0, t_fast, y, st);
+  };
+  if (!use_graph) return enqueue();
   if (!st) return SIM_ERR_ARG;
   std::vector<void*> key;
   key.push_back(c->ws);
+  key.push_back((void*)(intptr_t)b->mode);
   for (int r = 0; r < R; ++r) {
     key.push_back(spec0[r]);
     key.push_back(t_fast[r]);
@@ -1192,7 +1506,7 @@ sim_status sim_batch_run(sim_batch* b, void* const* spec0, void* const* t_fast, 
     s = dev(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     if (s != SIM_OK) return s;
     c->capturing = true;
-    const sim_status se = batch_enqueue(b, spec0, t_fast, y, st);
+    const sim_status se = enqueue();
     c->capturing = false;
     hipGraph_t graph;
     s = dev(hipStreamEndCapture(st, &graph));
@@ -1212,3 +1526,177 @@ sim_status sim_batch_run(sim_batch* b, void* const* spec0, void* const* t_fast, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Out-of-core runs (Sec. III.B, last two paragraphs): T_fast and Y stay in
+// host memory and the device holds caches of K spectra.  The paper fills a
+// device cache of spectra, copies it to host memory when full, and later
+// copies parts of the spectra back to post-process them.  Here each chunk's
+// IQ is formed on the device from the cache it has just filled (plus the
+// last spectrum of the previous chunk), so no spectrum travels back to the
+// device: per chunk of K update intervals, the compute stream fills one of
+// two cache buffers and runs the post-processing; a copy stream moves that
+// buffer's IQ (and spectra) to host memory while the next chunk computes into
+// the other buffer.
+
+struct sim_streamer {
+  sim_ctx* ctx;
+  sim_radar radar;
+  int K;                       // update intervals per chunk
+  size_t spec_bytes;           // one spectrum
+  size_t cache_bytes;          // one of the two buffers
+  hipStream_t copy_st;
+  hipEvent_t computed[2], copied[2], done;
+};
+
+namespace {
+
+size_t streamer_buffer_bytes(const sim_radar* r, int K, size_t cs) {
+  const size_t spec = (size_t)r->n_gates * r->n_doppler * cs;
+  const size_t y = (size_t)K * r->n_fast * r->n_gates * cs;
+  return align256((size_t)(K + 1) * spec) + align256(y);
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_streamer_destroy(sim_streamer* st);
+
+sim_status sim_streamer_create(sim_ctx* ctx, const sim_radar* radar, int32_t chunk_updates,
+                               sim_streamer** out) {
+  if (!out) return SIM_ERR_ARG;
+  *out = nullptr;
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (chunk_updates < 1) return SIM_ERR_SHAPE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  sim_streamer* st = new (std::nothrow) sim_streamer;
+  if (!st) return SIM_ERR_DEVICE;
+  st->ctx = ctx;
+  st->radar = *radar;
+  st->K = chunk_updates;
+  st->spec_bytes = (size_t)radar->n_gates * radar->n_doppler * csize(ctx);
+  st->cache_bytes = streamer_buffer_bytes(radar, chunk_updates, csize(ctx));
+  // every handle starts null so that a partial set-up can be released
+  st->copy_st = nullptr;
+  st->done = nullptr;
+  for (int b = 0; b < 2; ++b) st->computed[b] = st->copied[b] = nullptr;
+  bool ok = hipStreamCreateWithFlags(&st->copy_st, hipStreamNonBlocking) == hipSuccess;
+  for (int b = 0; b < 2 && ok; ++b) {
+    ok = hipEventCreateWithFlags(&st->computed[b], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&st->copied[b], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipEventCreateWithFlags(&st->done, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    (void)sim_streamer_destroy(st);
+    return SIM_ERR_DEVICE;
+  }
+  *out = st;
+  return SIM_OK;
+}
+
+sim_status sim_streamer_destroy(sim_streamer* st) {
+  if (!st) return SIM_OK;
+  sim_status s = use_device(st->ctx);
+  if (st->copy_st) {
+    if (hipStreamSynchronize(st->copy_st) != hipSuccess) s = SIM_ERR_DEVICE;
+    if (hipStreamDestroy(st->copy_st) != hipSuccess) s = SIM_ERR_DEVICE;
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (st->computed[b] && hipEventDestroy(st->computed[b]) != hipSuccess) s = SIM_ERR_DEVICE;
+    if (st->copied[b] && hipEventDestroy(st->copied[b]) != hipSuccess) s = SIM_ERR_DEVICE;
+  }
+  if (st->done && hipEventDestroy(st->done) != hipSuccess) s = SIM_ERR_DEVICE;
+  delete st;
+  return s;
+}
+
+sim_status sim_streamer_cache_size(const sim_streamer* st, size_t* bytes) {
+  if (!st || !bytes) return SIM_ERR_ARG;
+  *bytes = 2 * st->cache_bytes;
+  return SIM_OK;
+}
+
+sim_status sim_streamer_run(sim_streamer* st, const sim_grid* grid, const void* prepared,
+                            int32_t n_updates, void* t_fast_host, void* y_host, void* cache,
+                            size_t cache_bytes, void* stream) {
+  if (!st) return SIM_ERR_ARG;
+  sim_ctx* c = st->ctx;
+  const sim_radar* r = &st->radar;
+  WsLayout L;
+  sim_status s = common_checks(c, grid, r, &L);
+  if (s != SIM_OK) return s;
+  if (!prepared || !y_host || !cache) return SIM_ERR_ARG;
+  if (((uintptr_t)cache & 255) != 0) return SIM_ERR_ARG;
+  if (n_updates < 1) return SIM_ERR_SHAPE;
+  if (cache_bytes < 2 * st->cache_bytes) return SIM_ERR_WORKSPACE;
+  s = use_device(c);
+  if (s != SIM_OK) return s;
+  hipStream_t cs_ = (hipStream_t)stream;
+  const int K = st->K;
+  const size_t spec = st->spec_bytes;
+  const size_t y_row = (size_t)r->n_gates * csize(c);        // one pulse
+  const size_t y_off = align256((size_t)(K + 1) * spec);
+  char* buf[2] = {(char*)cache, (char*)cache + st->cache_bytes};
+  // both buffers start free: mark them copied on the copy stream, after
+  // everything already queued on the caller's stream
+  s = dev(hipEventRecord(st->done, cs_));
+  if (s == SIM_OK) s = dev(hipStreamWaitEvent(st->copy_st, st->done, 0));
+  for (int b = 0; b < 2 && s == SIM_OK; ++b) s = dev(hipEventRecord(st->copied[b], st->copy_st));
+  const int n_chunks = (n_updates + K - 1) / K;
+  for (int ch = 0; ch < n_chunks && s == SIM_OK; ++ch) {
+    const int b = ch & 1;
+    const int j0 = ch * K;                       // first spectrum of the chunk (slot 0)
+    const int k = std::min(K, n_updates - j0);   // update intervals (segments) of the chunk
+    char* specs = buf[b];
+    char* ycache = buf[b] + y_off;
+    s = dev(hipStreamWaitEvent(cs_, st->copied[b], 0));
+    if (s != SIM_OK) break;
+    // slot 0: spectrum j0, computed by the previous chunk (its last slot)
+    if (ch == 0) {
+      s = dev(simk::launch_clear(specs, spec, cs_));
+      if (s == SIM_OK) {
+        s = sim_update_and_accumulate_prepared(c, grid, prepared, r, 0.0, 0, specs, 1, nullptr,
+                                               nullptr, cs_);
+      }
+    } else {
+      const int kp = std::min(K, n_updates - (j0 - K));
+      s = dev(hipMemcpyAsync(specs, buf[b ^ 1] + (size_t)kp * spec, spec,
+                             hipMemcpyDeviceToDevice, cs_));
+    }
+    if (s != SIM_OK) break;
+    s = dev(simk::launch_clear(specs + spec, (size_t)k * spec, cs_));
+    for (int i = 1; i <= k && s == SIM_OK; ++i) {
+      const int j = j0 + i;
+      const double t = ((double)j * r->n_fast) / r->prf_hz;
+      s = sim_update_and_accumulate_prepared(c, grid, prepared, r, t, i, specs, k + 1, nullptr,
+                                             nullptr, cs_);
+    }
+    if (s == SIM_OK) s = sim_segments_to_iq(c, r, specs, k + 1, ycache, cs_);
+    if (s == SIM_OK) s = dev(hipEventRecord(st->computed[b], cs_));
+    if (s != SIM_OK) break;
+    // copies of this chunk on the copy stream
+    s = dev(hipStreamWaitEvent(st->copy_st, st->computed[b], 0));
+    if (s == SIM_OK)
+      s = dev(hipMemcpyAsync((char*)y_host + (size_t)j0 * r->n_fast * y_row, ycache,
+                             (size_t)k * r->n_fast * y_row, hipMemcpyDeviceToHost, st->copy_st));
+    if (s == SIM_OK && t_fast_host) {
+      const int first = ch == 0 ? 0 : 1;
+      s = dev(hipMemcpyAsync((char*)t_fast_host + (size_t)(j0 + first) * spec,
+                             specs + (size_t)first * spec, (size_t)(k + 1 - first) * spec,
+                             hipMemcpyDeviceToHost, st->copy_st));
+    }
+    if (s == SIM_OK) s = dev(hipEventRecord(st->copied[b], st->copy_st));
+  }
+  // join: the caller's stream waits for the last copies
+  sim_status sj = dev(hipEventRecord(st->done, st->copy_st));
+  if (sj == SIM_OK) sj = dev(hipStreamWaitEvent(cs_, st->done, 0));
+  return s != SIM_OK ? s : sj;
+}
+
+}  // extern "C"
+

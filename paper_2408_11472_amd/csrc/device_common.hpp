@@ -341,12 +341,23 @@ struct GridP {
   double dx, dy, x_origin, y_origin, gravity, sqrt_g;
 };
 
+// Look-up tables of the facet amplitude (device memory, one block per
+// context): a two-way complex antenna pattern on a u-v grid and the NRCS over
+// the local incidence angle; a null table means the closed form.
+struct TabP {
+  const void* ant;    // [nv][nu] complex (context precision) or null
+  const void* nrcs;   // [n_theta] real or null
+  int nu, nv, n_theta, pad;
+  double u0, inv_du, v0, inv_dv, inv_dtheta;
+};
+
 struct RadarP {
   double altitude, sat_x;
   double sat_y1, sat_y2;   // platform y at the two pulses of the pair
   double k2;               // 2 f_c / c
   double gate_spacing, window_start;
   double fresnel_over_mss, inv_mss, two_over_gamma, cell_area;
+  const TabP* tab;         // look-up tables, or null for the closed forms
   int G, N, log2N;
 };
 

@@ -40,10 +40,14 @@ namespace simk {
 // strip, rows in order, the pair (c(k), c(-k)) of each column of the strip,
 // so the loads of a wave are one contiguous run instead of CPB-element
 // pieces of rows and their mirrors.
+// Body of one column block: blk of nblk blocks (blockIdx.x and gridDim.x for
+// a plain launch, the work item and item count of a member in a batched one).
 template <typename Real, int LOG2NY, bool PREP>
-__global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
-colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
-               double t, double dt, const cplx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void colpass_body(const cplx<Real>* __restrict__ spec,
+                                             cplx<Real>* __restrict__ planes, const GridP& gp,
+                                             double t, double dt,
+                                             const cplx<Real>* __restrict__ tw, int blk,
+                                             int nblk) {
   constexpr int E = 16;
   constexpr int ny = 1 << LOG2NY;
   constexpr int TPS = ny / E;
@@ -56,9 +60,7 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
   // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
   // contiguous run of (strip, group) items so that the two groups of a strip
   // and neighbouring strips, which share cache lines, meet in the same L2.
-  const int nblk = gridDim.x;
-  const int item = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
-                                   : blockIdx.x;
+  const int item = (nblk % 8 == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
   const int strip = item >> 1, group = item & 1;
   const int ix = strip * CPB + c;          // kx index, 0 <= ix < half width
   const bool live = ix < nx / 2;           // the Nyquist column carries no wave
@@ -197,6 +199,13 @@ colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ pla
       }
     }
   }
+}
+
+template <typename Real, int LOG2NY, bool PREP>
+__global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
+colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
+               double t, double dt, const cplx<Real>* __restrict__ tw) {
+  colpass_body<Real, LOG2NY, PREP>(spec, planes, gp, t, dt, tw, blockIdx.x, gridDim.x);
 }
 
 // The prepared spectrum of the column pass: for each column ix of the half
@@ -633,9 +642,10 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
 }
 
 template <typename Real, int LOG2NX>
-__global__ void __launch_bounds__(row_threads(LOG2NX))
-rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs<Real> out,
-                      const cplx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void rowpass_facets_body(const cplx<Real>* __restrict__ planes,
+                                                    const GridP& gp, const FacetPtrs<Real>& out,
+                                                    const cplx<Real>* __restrict__ tw, int blk,
+                                                    int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int nx = 1 << LOG2NX;
   constexpr int TPR = row_tpr(LOG2NX);
@@ -656,19 +666,17 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
   // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
   // contiguous run of row chunks, so that the chunks sharing a plane tile
   // (and its cache lines) are read through the same L2 at about the same time.
-  const int nblk = gridDim.x;
-  const int q = (nblk % 8 == 0) ? (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
-                                : blockIdx.x;
+  const int q = (nblk % 8 == 0) ? (blk & 7) * (nblk >> 3) + (blk >> 3) : blk;
 
   // with two exchange rows, the own columns of each transform's input are
   // loaded one transform ahead (first: transform 3 of the first row)
   PairRegs<Real> pre;
   if (row_facets_pp(LOG2NX, sizeof(cplx<Real>)))
     load_pair_direct<Real, LOG2NX>(planes, psz, 3, q * RPB + rl, tr, gp, pre);
-  for (int iy0 = q * RPB; iy0 < ny; iy0 += gridDim.x * RPB) {
+  for (int iy0 = q * RPB; iy0 < ny; iy0 += nblk * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
-    const int iy_next = iy0 + gridDim.x * RPB < ny ? iy0 + gridDim.x * RPB + rl : -1;
+    const int iy_next = iy0 + nblk * RPB < ny ? iy0 + nblk * RPB + rl : -1;
     // each facet quantity is stored as soon as it is formed
     auto emit = [&](int field, const Real* val) {
       if (valid) {
@@ -682,6 +690,13 @@ rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs
     row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
                                     F, emit, lrow2, &pre);
   }
+}
+
+template <typename Real, int LOG2NX>
+__global__ void __launch_bounds__(row_threads(LOG2NX))
+rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs<Real> out,
+                      const cplx<Real>* __restrict__ tw) {
+  rowpass_facets_body<Real, LOG2NX>(planes, gp, out, tw, blockIdx.x, gridDim.x);
 }
 
 // Shared LDS carve-up for the accumulating kernels: [fft rows][window][state]
@@ -789,14 +804,19 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
 // ---------------------------------------------------------------------------
 // Scatterers from a facet SoA: band = contiguous facet range, chunks of
 // EA * blockDim facets.
-constexpr int EA = 8;
+#ifndef SIMK_EA
+#define SIMK_EA 8
+#endif
+constexpr int EA = SIMK_EA;
 
 template <typename Real>
-__global__ void __launch_bounds__(acc_threads(sizeof(cplx<Real>)))
-accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
-                         cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out) {
+__device__ __forceinline__ void accumulate_facets_body(const FacetPtrs<Real>& fac,
+                                                       const GridP& gp, const RadarP& rp,
+                                                       const WinP& wp,
+                                                       cplx<Real>* __restrict__ Tj,
+                                                       int32_t* __restrict__ code_out,
+                                                       int band) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int band = blockIdx.x;
   WinCtx<Real> w = win_ctx<Real>(smem_raw, 0, rp, wp, Tj, band);
   win_init(w, rp, wp);
   uint32_t cnt[5] = {0, 0, 0, 0, 0};
@@ -828,6 +848,13 @@ accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
   store_band_counts(wp, band, cnt, overflow, w.red);
 }
 
+template <typename Real>
+__global__ void __launch_bounds__(acc_threads(sizeof(cplx<Real>)))
+accumulate_facets_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp, WinP wp,
+                         cplx<Real>* __restrict__ Tj, int32_t* __restrict__ code_out) {
+  accumulate_facets_body<Real>(fac, gp, rp, wp, Tj, code_out, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Ordered reduction of the band windows into T_fast[j]: one block per gate.
 // The slots covering the gate are compacted in slot order and cut into
@@ -840,9 +867,10 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceBatch = 8;
 
 template <typename Real>
-__global__ void __launch_bounds__(kReduceThreads)
-reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
-                       unsigned long long* __restrict__ counters, int n_acc) {
+__device__ __forceinline__ void reduce_partials_body(const RadarP& rp, const WinP& wp,
+                                                     cplx<Real>* __restrict__ Tj,
+                                                     unsigned long long* __restrict__ counters,
+                                                     int n_acc, int g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nslots = wp.n_bands * wp.S;
   const int N = rp.N, WK = wp.WK;
@@ -850,7 +878,6 @@ reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
   int* list = reinterpret_cast<int*>(acc + (size_t)n_acc * N);             // [nslots]
   int* lk0 = list + nslots;                                                // [nslots]
   __shared__ int wcount[16];
-  const int g = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < n_acc * N; i += blockDim.x) acc[i] = mk<double>(0.0, 0.0);
   int base = 0;
@@ -918,7 +945,7 @@ reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
     t.y = (Real)((double)t.y + ay);
     Tj[(size_t)g * N + k] = t;
   }
-  if (blockIdx.x == 0 && counters != nullptr) {
+  if (g == 0 && counters != nullptr) {
     unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < wp.n_bands; b += blockDim.x)
       for (int i = 0; i < 6; ++i) v[i] += wp.bandcnt[(size_t)b * 8 + i];
@@ -934,6 +961,98 @@ reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
       for (int w2 = 0; w2 < nw; ++w2) sum += red[threadIdx.x][w2];
       counters[threadIdx.x] += sum;
     }
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kReduceThreads)
+reduce_partials_kernel(RadarP rp, WinP wp, cplx<Real>* __restrict__ Tj,
+                       unsigned long long* __restrict__ counters, int n_acc) {
+  reduce_partials_body<Real>(rp, wp, Tj, counters, n_acc, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launches.  The members of a batch that share a grid
+// shape run each phase of an update (column pass, facet row pass, facet
+// accumulate, ordered reduce) in one launch of a grid sized to what the GPU
+// holds at once.  Work items are (member, block of that member), numbered
+// member-major; blocks take them from a device counter (one counter per
+// launch, cleared with the batch) and run them until the counter passes the
+// item count, which every block reaches.  The per-member parameters of the
+// update are read from a descriptor array in device memory.
+
+// Next work item of the block (uniform over the block): thread 0 takes it
+// from the counter, the block reads it after a barrier; the second barrier
+// keeps it until every thread has it (and orders the previous item's LDS
+// use before the next item's).
+__device__ __forceinline__ int next_item(int* queue, int* s_item) {
+  if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1);
+  __syncthreads();
+  const int item = __builtin_amdgcn_readfirstlane(*s_item);
+  __syncthreads();
+  return item;
+}
+
+template <typename Real, int LOG2NY>
+__global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
+colpass_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
+                       int* __restrict__ queue, const cplx<Real>* __restrict__ tw) {
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const int m = item / per, blk = item - m * per;
+    const BatchMember& b = mem[m];
+    colpass_body<Real, LOG2NY, true>((const cplx<Real>*)b.spec, (cplx<Real>*)b.planes, b.gp,
+                                     b.t, b.dt, tw, blk, per);
+  }
+}
+
+template <typename Real, int LOG2NX>
+__global__ void __launch_bounds__(row_threads(LOG2NX))
+rowpass_facets_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
+                              int* __restrict__ queue, const cplx<Real>* __restrict__ tw) {
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const int m = item / per, blk = item - m * per;
+    const BatchMember& b = mem[m];
+    FacetPtrs<Real> fp;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)b.fac[i];
+    rowpass_facets_body<Real, LOG2NX>((const cplx<Real>*)b.planes, b.gp, fp, tw, blk, per);
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(acc_threads(sizeof(cplx<Real>)))
+accumulate_facets_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
+                                 int* __restrict__ queue) {
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const int m = item / per, blk = item - m * per;
+    const BatchMember& b = mem[m];
+    FacetPtrs<Real> fp;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)b.fac[i];
+    accumulate_facets_body<Real>(fp, b.gp, b.rp, b.wp, (cplx<Real>*)b.Tj, nullptr, blk);
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kReduceThreads)
+reduce_partials_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
+                               int* __restrict__ queue, int n_acc) {
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const int m = item / per, blk = item - m * per;
+    const BatchMember& b = mem[m];
+    reduce_partials_body<Real>(b.rp, b.wp, (cplx<Real>*)b.Tj, nullptr, n_acc, blk);
   }
 }
 
@@ -1168,6 +1287,11 @@ accumulate_adjoint_kernel(FacetPtrs<Real> fac, GridP gp, RadarP rp,
 // The grid parameters with the plane tile geometry of this precision.
 template <typename Real>
 static GridP with_tiles(const GridP& gp) {
+  return grid_with_tiles<Real>(gp);
+}
+
+template <typename Real>
+GridP grid_with_tiles(const GridP& gp) {
   GridP g = gp;
   g.tlw = tile_lw(gp.log2ny, sizeof(cplx<Real>));
   g.tlh = tile_lh(gp.log2ny, sizeof(cplx<Real>));
@@ -1183,12 +1307,13 @@ static hipError_t colpass_t(const void* spec, void* planes, const GridP& gp, dou
     return hipErrorInvalidValue;
   } else {
     const int strips = (1 << half_lw(gp.log2nx, L, cs)) / col_cpb(L, cs);
+    const int blocks = 2 * strips;
     if (prepared)
-      hipLaunchKernelGGL((colpass_kernel<Real, L, true>), dim3(2 * strips),
+      hipLaunchKernelGGL((colpass_kernel<Real, L, true>), dim3(blocks),
                          dim3(col_threads(L, cs)), col_lds(L, cs), st, (const cplx<Real>*)spec,
                          (cplx<Real>*)planes, with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
     else
-      hipLaunchKernelGGL((colpass_kernel<Real, L, false>), dim3(2 * strips),
+      hipLaunchKernelGGL((colpass_kernel<Real, L, false>), dim3(blocks),
                          dim3(col_threads(L, cs)), col_lds(L, cs), st, (const cplx<Real>*)spec,
                          (cplx<Real>*)planes, with_tiles<Real>(gp), t, dt, (const cplx<Real>*)tw);
     return hipGetLastError();
@@ -1295,6 +1420,98 @@ hipError_t launch_reduce(const RadarP& rp, const WinP& wp, void* Tj, unsigned lo
   return hipGetLastError();
 }
 
+// Grid of a persistent launch: the blocks the device holds at once (at the
+// kernel's occupancy), at most one per item.
+static int persistent_grid(const void* kernel, int threads, size_t lds, int n_items) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 256;
+    per_cu = 1;
+  }
+  if (per_cu < 1) per_cu = 1;
+  const long cap = (long)cus * per_cu;
+  return (int)(n_items < cap ? n_items : cap);
+}
+
+template <typename Real, int L>
+static hipError_t colpass_batched_t(const BatchMember* mem, int n_mem, const GridP& gp,
+                                    int* queue, const void* tw, hipStream_t st) {
+  constexpr int cs = sizeof(cplx<Real>);
+  if constexpr (col_lds(L, cs) > kLdsBudget) {
+    return hipErrorInvalidValue;
+  } else {
+    const int strips = (1 << half_lw(gp.log2nx, L, cs)) / col_cpb(L, cs);
+    const int per = 2 * strips;
+    const int n = n_mem * per;
+    const void* k = (const void*)colpass_batched_kernel<Real, L>;
+    const int grid = persistent_grid(k, col_threads(L, cs), col_lds(L, cs), n);
+    hipLaunchKernelGGL((colpass_batched_kernel<Real, L>), dim3(grid), dim3(col_threads(L, cs)),
+                       col_lds(L, cs), st, mem, per, n, queue, (const cplx<Real>*)tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename Real, int L>
+static hipError_t rowpass_batched_t(const BatchMember* mem, int n_mem, const GridP& gp,
+                                    int* queue, const void* tw, hipStream_t st) {
+  constexpr int cs = sizeof(cplx<Real>);
+  const int per = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
+  const int n = n_mem * per;
+  const void* k = (const void*)rowpass_facets_batched_kernel<Real, L>;
+  const int grid = persistent_grid(k, row_threads(L), row_facets_lds(L, cs), n);
+  hipLaunchKernelGGL((rowpass_facets_batched_kernel<Real, L>), dim3(grid), dim3(row_threads(L)),
+                     row_facets_lds(L, cs), st, mem, per, n, queue, (const cplx<Real>*)tw);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_update_batched(const BatchMember* mem, int n_mem, const GridP& gp,
+                                 const RadarP& rp, const WinP& wp, size_t acc_lds, int* queues,
+                                 const void* tw, hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (gp.log2ny) {
+#define SIMK_CASE(L) \
+  case L: e = colpass_batched_t<Real, L>(mem, n_mem, gp, queues + 0, tw, st); break;
+    SIMK_COL_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+    default: break;
+  }
+  if (e != hipSuccess) return e;
+  e = hipErrorInvalidValue;
+  switch (gp.log2nx) {
+#define SIMK_CASE(L) \
+  case L: e = rowpass_batched_t<Real, L>(mem, n_mem, gp, queues + 1, tw, st); break;
+    SIMK_ROW_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+    default: break;
+  }
+  if (e != hipSuccess) return e;
+  {
+    const int per = wp.n_bands, n = n_mem * per;
+    const int threads = acc_threads(sizeof(cplx<Real>));
+    const void* k = (const void*)accumulate_facets_batched_kernel<Real>;
+    const int grid = persistent_grid(k, threads, acc_lds, n);
+    hipLaunchKernelGGL(accumulate_facets_batched_kernel<Real>, dim3(grid), dim3(threads),
+                       acc_lds, st, mem, per, n, queues + 2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int n_acc = (int)(65536 / ((size_t)rp.N * sizeof(cplx<double>)));
+  if (n_acc > kReduceThreads / 64) n_acc = kReduceThreads / 64;
+  if (n_acc < 1) n_acc = 1;
+  const size_t lds = (size_t)n_acc * rp.N * sizeof(cplx<double>) +
+                     (size_t)2 * wp.n_bands * wp.S * sizeof(int);
+  const int per = rp.G, n = n_mem * per;
+  const void* k = (const void*)reduce_partials_batched_kernel<Real>;
+  const int grid = persistent_grid(k, kReduceThreads, lds, n);
+  hipLaunchKernelGGL(reduce_partials_batched_kernel<Real>, dim3(grid), dim3(kReduceThreads), lds,
+                     st, mem, per, n, queues + 3, n_acc);
+  return hipGetLastError();
+}
+
 template <typename Real>
 hipError_t launch_segments_to_iq(const void* T, void* Y, int G, int N, int log2N, int n_fast,
                                  int window, int n_seg, int GB, const void* tw, hipStream_t st) {
@@ -1394,6 +1611,17 @@ static hipError_t set_attributes(int lds) {
 #undef SIMK_CASE
   set((const void*)accumulate_facets_kernel<Real>);
   set((const void*)reduce_partials_kernel<Real>);
+#define SIMK_CASE(L)                                                      \
+  if constexpr (col_lds(L, sizeof(cplx<Real>)) <= kLdsBudget) {           \
+    set((const void*)colpass_batched_kernel<Real, L>);                    \
+  }
+  SIMK_COL_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+#define SIMK_CASE(L) set((const void*)rowpass_facets_batched_kernel<Real, L>);
+  SIMK_ROW_SIZES(SIMK_CASE)
+#undef SIMK_CASE
+  set((const void*)accumulate_facets_batched_kernel<Real>);
+  set((const void*)reduce_partials_batched_kernel<Real>);
   set((const void*)segments_to_iq_kernel<Real>);
   set((const void*)segments_to_iq_adjoint_kernel<Real>);
   return e;
@@ -1428,7 +1656,11 @@ hipError_t init_kernel_attributes(int lds) {
   template hipError_t launch_segments_to_iq_adjoint<R>(const void*, void*, int, int, int, int,  \
                                                        int, int, int, const void*, hipStream_t); \
   template hipError_t launch_accumulate_adjoint<R>(void* const*, const GridP&, const RadarP&,   \
-                                                   const void*, void*, void*, void*, hipStream_t);
+                                                   const void*, void*, void*, void*, hipStream_t); \
+  template hipError_t launch_update_batched<R>(const BatchMember*, int, const GridP&,           \
+                                               const RadarP&, const WinP&, size_t, int*,        \
+                                               const void*, hipStream_t);                       \
+  template GridP grid_with_tiles<R>(const GridP&);
 
 SIMK_INSTANTIATE(float)
 SIMK_INSTANTIATE(double)

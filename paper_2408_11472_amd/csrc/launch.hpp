@@ -115,7 +115,10 @@ __host__ __device__ constexpr bool row_stage_fused(int log2nx, int cs) {
 // Threads per block of the facet accumulate (one band window per block):
 // 512 in float, 256 in double (measured on 4096^2: 287 vs 340 us in float,
 // 388 vs 466 us in double).
-__host__ __device__ constexpr int acc_threads(int cs) { return cs == 8 ? 512 : 256; }
+#ifndef SIMK_ACC_THREADS32
+#define SIMK_ACC_THREADS32 512
+#endif
+__host__ __device__ constexpr int acc_threads(int cs) { return cs == 8 ? SIMK_ACC_THREADS32 : 256; }
 
 // LDS of a window context after the partial spectra: 8 state ints, then the
 // reduction scratch (6 counters x 16 waves for the band counts; the min/max
@@ -137,6 +140,30 @@ struct RowPlan {
   size_t front_bytes; // fft_bytes + staging row (fused kernel)
   size_t acc_bytes;   // front_bytes + window + state (fused kernel)
 };
+
+// One member of a persistent batched launch at one update: its grid (with
+// the plane tiles set, grid_with_tiles), platform, windows and buffers.
+struct BatchMember {
+  GridP gp;
+  RadarP rp;
+  WinP wp;
+  const void* spec;   // prepared spectrum
+  void* planes;       // half planes (workspace)
+  void* fac[9];       // facet SoA (workspace)
+  void* Tj;           // T_fast[j] of the member
+  double t, dt;       // first pulse of the pair, pair interval
+};
+
+template <typename Real>
+GridP grid_with_tiles(const GridP& gp);
+
+// The four per-update phases of the split row path for n_mem members of one
+// grid shape (mem: device array), each one persistent launch taking work
+// items from its counter (queues[0..3], zero before the launch).
+template <typename Real>
+hipError_t launch_update_batched(const BatchMember* mem, int n_mem, const GridP& gp,
+                                 const RadarP& rp, const WinP& wp, size_t acc_lds, int* queues,
+                                 const void* tw, hipStream_t st);
 
 hipError_t init_kernel_attributes(int lds_bytes);
 hipError_t launch_clear(void* p, size_t bytes, hipStream_t st);
@@ -179,5 +206,12 @@ template <typename Real>
 hipError_t launch_accumulate_adjoint(void* const* fac, const GridP& gp, const RadarP& rp,
                                      const void* Tbar_j, void* gh, void* gsx, void* gsy,
                                      hipStream_t st);
+
+// Delay-Doppler processing (dd.hip).
+template <typename Real>
+hipError_t launch_delay_doppler(const void* y, int G, int M, int n_bursts, int centroid_mode,
+                                double centroid_given, double mig, int migration, void* beams,
+                                void* centroid, void* beam_power, void* waveform,
+                                const void* tw, hipStream_t st);
 
 }  // namespace simk

@@ -7,6 +7,50 @@
 
 namespace simk {
 
+// Bilinear interpolation of the antenna table at (u, v) and linear
+// interpolation of the NRCS table at theta_l = atan(sqrt(tan^2)) (cell index
+// from the fractional grid coordinate, the last node belonging to the cell
+// before it, zero outside the table); a missing table uses its closed form.
+// Returns sqrt(sigma0 A) G.
+template <typename Real>
+__device__ __forceinline__ cplx<Real> tabulated_amplitude(const TabP& T, const RadarP& rp,
+                                                          Real tan2, Real sec2, Real sin2, Real u,
+                                                          Real v, Real area) {
+  Real sigma0;
+  if (T.nrcs) {
+    const Real* s = (const Real*)T.nrcs;
+    const Real f = atan(approx_sqrt(tan2)) * (Real)T.inv_dtheta;
+    const int n = T.n_theta;
+    sigma0 = (Real)0;
+    if (f >= (Real)0 && f <= (Real)(n - 1)) {
+      const int i = min((int)f, n - 2);
+      const Real w = f - (Real)i;
+      sigma0 = ((Real)1 - w) * s[i] + w * s[i + 1];
+    }
+  } else {
+    sigma0 = (Real)rp.fresnel_over_mss * sec2 * sec2 * exp(-(Real)rp.inv_mss * tan2);
+  }
+  const Real amp = approx_sqrt(sigma0 * area);
+  if (!T.ant) {
+    const Real ga = exp(-(Real)rp.two_over_gamma * sin2);
+    return mk<Real>(amp * ga, (Real)0);
+  }
+  const cplx<Real>* a = (const cplx<Real>*)T.ant;
+  const Real fu = (u - (Real)T.u0) * (Real)T.inv_du;
+  const Real fv = (v - (Real)T.v0) * (Real)T.inv_dv;
+  if (!(fu >= (Real)0 && fu <= (Real)(T.nu - 1) && fv >= (Real)0 && fv <= (Real)(T.nv - 1)))
+    return mk<Real>((Real)0, (Real)0);
+  const int iu = min((int)fu, T.nu - 2), iv = min((int)fv, T.nv - 2);
+  const Real wu = fu - (Real)iu, wv = fv - (Real)iv;
+  const cplx<Real>* r0 = a + (size_t)iv * T.nu + iu;
+  const cplx<Real>* r1 = r0 + T.nu;
+  const Real w00 = ((Real)1 - wv) * ((Real)1 - wu), w01 = ((Real)1 - wv) * wu;
+  const Real w10 = wv * ((Real)1 - wu), w11 = wv * wu;
+  const Real gx = w00 * r0[0].x + w01 * r0[1].x + w10 * r1[0].x + w11 * r1[1].x;
+  const Real gy = w00 * r0[0].y + w01 * r0[1].y + w10 * r1[0].y + w11 * r1[1].y;
+  return mk<Real>(amp * gx, amp * gy);
+}
+
 // Scatterer of one facet.  Returns g * N + bin for an illuminated facet, or
 // a negative drop code (tested in the order nonfinite, folded, out of
 // window, backfacing).  The range, gate, Doppler bin and carrier phase are
@@ -72,6 +116,17 @@ __device__ __forceinline__ int scatterer(const RadarP& rp, const GridP& gp, int 
   const Real fx = (Real)ddx, fy = (Real)ddy;
   const Real sin2 = (fx * fx + fy * fy) * (ir * ir);
   const Real hr = (Real)rp.altitude * ir;
+  if (rp.tab) {
+    // tabulated NRCS and/or antenna pattern (complex amplitude)
+    const Real area = jac * approx_sqrt((Real)1 + sx * sx + sy * sy) * (Real)rp.cell_area;
+    const cplx<Real> a = tabulated_amplitude<Real>(*rp.tab, rp, tan2, sec2, sin2,
+                                                   (Real)(-ddx / r), (Real)(-ddy / r), area);
+    Real sn, cs;
+    sincos_pi((Real)2 * (Real)frac, &sn, &cs);
+    const Real h2 = hr * hr;
+    C = cmul(mk<Real>(a.x * h2, a.y * h2), mk<Real>(cs, -sn));
+    return g * rp.N + kbin;
+  }
   // a = sqrt(sigma0 A) Ga (H/R)^2 with sigma0 = (|G0|^2/mss) sec^4 exp(-tan^2/mss)
   // and Ga = exp(-(2/gamma) sin^2): one exponential for both
   const Real area = jac * approx_sqrt((Real)1 + sx * sx + sy * sy) * (Real)rp.cell_area;
@@ -91,9 +146,10 @@ __device__ __forceinline__ int scatterer(const RadarP& rp, const GridP& gp, int 
 // facets does not fit the current bins, the window is flushed to the next of
 // the band's S partial slots in the workspace and re-centred on the chunk;
 // a chunk wider than WK bins is processed in several windows.  Slots are
-// later summed per gate, in slot order, by the reduce kernel, so the result
-// does not depend on scheduling.  A band that runs out of slots merges the
-// extra windows into T with atomics and counts them (window_overflow).
+// later summed per gate, in slot order, by the reduce kernel (a fixed
+// association over the bands; within a window cell the atomics add in
+// scheduling order).  A band that runs out of slots merges the extra windows
+// into T with atomics and counts them (window_overflow).
 //
 // LDS state (ints): 0 active, 1 k0, 2 g_lo, 3 g_hi, 4 next slot, 5 dirty.
 

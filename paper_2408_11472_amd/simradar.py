@@ -14,7 +14,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsimradar.so")
+# SIMRADAR_LIB selects another build of the same library (for instance one
+# compiled with other launch constants); the default is the in-tree build.
+LIB_PATH = os.environ.get("SIMRADAR_LIB") or os.path.join(HERE, "libsimradar.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
@@ -50,7 +52,9 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
             "sim_range_doppler_accumulate_adjoint",
             "sim_batch_create", "sim_batch_destroy", "sim_batch_workspace_size",
-            "sim_batch_run", "sim_set_tuning",
+            "sim_batch_run", "sim_set_tuning", "sim_delay_doppler", "sim_set_tables",
+            "sim_streamer_create", "sim_streamer_destroy", "sim_streamer_cache_size",
+            "sim_streamer_run", "sim_batch_set_mode", "sim_batch_set_tuning",
             "sim_profile_enable", "sim_profile_read")
 
 SIM_TUNE_ROW_BANDS = 0
@@ -58,7 +62,9 @@ SIM_TUNE_ROW_PATH = 1
 SIM_ROW_PATH_AUTO, SIM_ROW_PATH_FUSED, SIM_ROW_PATH_SPLIT = 0, 1, 2
 
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
-                "reduce_partials", "segments_to_iq", "adjoint", "prepare")
+                "reduce_partials", "segments_to_iq", "adjoint", "prepare", "delay_doppler",
+                "batched_update")
+SIM_DD_CENTROID_GIVEN, SIM_DD_CENTROID_ESTIMATE = 0, 1
 
 
 class sim_grid(ctypes.Structure):
@@ -85,8 +91,23 @@ class sim_facets(ctypes.Structure):
 
 
 class sim_kernel_times(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
+    _fields_ = [("ms", ctypes.c_double * len(KERNEL_KINDS)),
+                ("launches", ctypes.c_uint64 * len(KERNEL_KINDS)),
                 ("dropped", ctypes.c_uint64)]
+
+
+class sim_tables(ctypes.Structure):
+    _fields_ = [("antenna", ctypes.c_void_p), ("nu", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("u0", ctypes.c_double), ("du", ctypes.c_double), ("v0", ctypes.c_double),
+                ("dv", ctypes.c_double), ("nrcs", ctypes.c_void_p),
+                ("n_theta", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dtheta", ctypes.c_double)]
+
+
+class sim_dd_params(ctypes.Structure):
+    _fields_ = [("burst", ctypes.c_int32), ("centroid_mode", ctypes.c_int32),
+                ("centroid", ctypes.c_double), ("migration", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -140,6 +161,17 @@ _sig = {
     "sim_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                      ctypes.POINTER(_P), ctypes.c_int, _P]),
     "sim_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "sim_set_tables": (ctypes.c_int, [_P, ctypes.POINTER(sim_tables)]),
+    "sim_batch_set_mode": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sim_batch_set_tuning": (ctypes.c_int, [_P, _I, ctypes.c_int, ctypes.c_int]),
+    "sim_streamer_create": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _I,
+                                           ctypes.POINTER(_P)]),
+    "sim_streamer_destroy": (ctypes.c_int, [_P]),
+    "sim_streamer_cache_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "sim_streamer_run": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P, _I, _P, _P, _P,
+                                        ctypes.c_size_t, _P]),
+    "sim_delay_doppler": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I,
+                                         ctypes.POINTER(sim_dd_params), _P, _P, _P, _P, _P]),
     "sim_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "sim_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(sim_kernel_times)]),
 }
@@ -275,6 +307,55 @@ def sim_range_doppler_accumulate_adjoint(ctx, grid, facets, radar, t, j, t_bar_p
                                                      ctypes.byref(facets), ctypes.byref(radar),
                                                      t, j, t_bar_ptr, n_spec, gh_ptr, gsx_ptr,
                                                      gsy_ptr, stream))
+
+
+def sim_delay_doppler(ctx, radar, y_ptr, n_pulses, params: sim_dd_params, beams_ptr,
+                      centroid_ptr, beam_power_ptr, waveform_ptr, stream) -> None:
+    _check("sim_delay_doppler",
+           _lib.sim_delay_doppler(ctx, ctypes.byref(radar), y_ptr, n_pulses,
+                                  ctypes.byref(params), beams_ptr, centroid_ptr,
+                                  beam_power_ptr, waveform_ptr, stream))
+
+
+SIM_BATCH_LANES, SIM_BATCH_PERSISTENT = 1, 2
+
+
+def sim_batch_set_mode(batch, mode) -> None:
+    _check("sim_batch_set_mode", _lib.sim_batch_set_mode(batch, int(mode)))
+
+
+def sim_batch_set_tuning(batch, member, key, value) -> None:
+    _check("sim_batch_set_tuning", _lib.sim_batch_set_tuning(batch, int(member), int(key),
+                                                              int(value)))
+
+
+def sim_set_tables(ctx, tables) -> None:
+    _check("sim_set_tables",
+           _lib.sim_set_tables(ctx, None if tables is None else ctypes.byref(tables)))
+
+
+def sim_streamer_create(ctx, radar, chunk_updates) -> int:
+    h = _P()
+    _check("sim_streamer_create",
+           _lib.sim_streamer_create(ctx, ctypes.byref(radar), chunk_updates, ctypes.byref(h)))
+    return h.value
+
+
+def sim_streamer_destroy(streamer) -> None:
+    _check("sim_streamer_destroy", _lib.sim_streamer_destroy(streamer))
+
+
+def sim_streamer_cache_size(streamer) -> int:
+    n = ctypes.c_size_t(0)
+    _check("sim_streamer_cache_size", _lib.sim_streamer_cache_size(streamer, ctypes.byref(n)))
+    return n.value
+
+
+def sim_streamer_run(streamer, grid, prepared_ptr, n_updates, t_host_ptr, y_host_ptr,
+                     cache_ptr, cache_bytes, stream) -> None:
+    _check("sim_streamer_run",
+           _lib.sim_streamer_run(streamer, ctypes.byref(grid), prepared_ptr, n_updates,
+                                 t_host_ptr, y_host_ptr, cache_ptr, cache_bytes, stream))
 
 
 def sim_set_tuning(ctx, key, value) -> None:
@@ -578,6 +659,98 @@ class Simulator:
             n_spec, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), self._stream(stream))
         return {"h": out[0], "sx": out[1], "sy": out[2]}
 
+    def set_tables(self, antenna=None, u0=0.0, du=1.0, v0=0.0, dv=1.0, nrcs=None, dtheta=1.0):
+        """Look-up tables of the facet amplitude (sim_set_tables): antenna
+        [nv][nu] complex and/or nrcs [n_theta] real device tensors of the
+        context's precision, kept referenced by this object; both None
+        restores the closed forms."""
+        if antenna is None and nrcs is None:
+            sim_set_tables(self.ctx, None)
+            self._tables = None
+            return
+        t = sim_tables(reserved=0)
+        if antenna is not None:
+            self._need(antenna, self.complex_dtype, None, "antenna")
+            if antenna.dim() != 2:
+                raise ValueError("antenna: expected a [nv][nu] tensor")
+            t.antenna = antenna.data_ptr()
+            t.nv, t.nu = int(antenna.shape[0]), int(antenna.shape[1])
+            t.u0, t.du, t.v0, t.dv = float(u0), float(du), float(v0), float(dv)
+        if nrcs is not None:
+            self._need(nrcs, self.real_dtype, None, "nrcs")
+            if nrcs.dim() != 1:
+                raise ValueError("nrcs: expected a [n_theta] tensor")
+            t.nrcs = nrcs.data_ptr()
+            t.n_theta = int(nrcs.shape[0])
+            t.dtheta = float(dtheta)
+        sim_set_tables(self.ctx, t)
+        self._tables = (antenna, nrcs)
+
+    def run_streamed(self, prepared, n_updates, chunk_updates, t_host=None, y_host=None,
+                     keep_spectra=True, stream=None):
+        """A whole run with T_fast and Y in (pinned) host memory and device
+        caches of chunk_updates update intervals (sim_streamer_*).  Returns
+        (T_host or None, Y_host) once the stream has completed."""
+        t = self.torch
+        r = self.radar
+        n_spec = n_updates + 1
+        if y_host is None:
+            y_host = t.empty((n_updates * r.n_fast, r.n_gates), dtype=self.complex_dtype,
+                             pin_memory=True)
+        if keep_spectra and t_host is None:
+            t_host = t.empty((n_spec, r.n_gates, r.n_doppler), dtype=self.complex_dtype,
+                             pin_memory=True)
+        for name, x, shape in (("y_host", y_host, (n_updates * r.n_fast, r.n_gates)),
+                               ("t_host", t_host, (n_spec, r.n_gates, r.n_doppler))):
+            if x is None:
+                continue
+            if x.is_cuda or x.dtype != self.complex_dtype or not x.is_contiguous() or \
+                    tuple(x.shape) != shape:
+                raise ValueError(f"{name}: expected a contiguous host {self.complex_dtype} "
+                                 f"tensor of shape {shape}")
+        pptr = self._need(prepared, self.complex_dtype, (self._prepared_elems(),), "prepared")
+        s = stream if stream is not None else t.cuda.current_stream(self.device)
+        st = sim_streamer_create(self.ctx, self.radar, int(chunk_updates))
+        try:
+            nbytes = sim_streamer_cache_size(st)
+            cache = t.empty(nbytes + 256, dtype=t.uint8, device=self.device)
+            cptr = (cache.data_ptr() + 255) & ~255
+            sim_streamer_run(st, self.grid, pptr, int(n_updates),
+                             None if t_host is None else t_host.data_ptr(), y_host.data_ptr(),
+                             cptr, nbytes, s.cuda_stream)
+        finally:
+            # the cache and the host buffers stay referenced until the stream is done
+            s.synchronize()
+            sim_streamer_destroy(st)
+        return t_host, y_host
+
+    def delay_doppler(self, y, burst=64, centroid=None, migration=True, stream=None):
+        """Delay-Doppler processing of the IQ y [n_pulses][G] (sim_delay_doppler):
+        returns dict(beams [n_bursts][burst][G] complex, centroid [n_bursts],
+        beam_power [burst][G], waveform [G]).  centroid=None estimates it per
+        burst, a number is used as given (cycles per pulse)."""
+        r = self.radar
+        n_pulses = y.shape[0]
+        nb = n_pulses // burst
+        t = self.torch
+        out = {"beams": t.empty((nb, burst, r.n_gates), dtype=self.complex_dtype,
+                                device=self.device),
+               "centroid": t.empty(nb, dtype=self.real_dtype, device=self.device),
+               "beam_power": t.empty((burst, r.n_gates), dtype=self.real_dtype,
+                                     device=self.device),
+               "waveform": t.empty(r.n_gates, dtype=self.real_dtype, device=self.device)}
+        p = sim_dd_params(burst=int(burst),
+                          centroid_mode=SIM_DD_CENTROID_ESTIMATE if centroid is None
+                          else SIM_DD_CENTROID_GIVEN,
+                          centroid=0.0 if centroid is None else float(centroid),
+                          migration=1 if migration else 0, reserved=0)
+        sim_delay_doppler(self.ctx, self.radar,
+                          self._need(y, self.complex_dtype, (n_pulses, r.n_gates), "y"),
+                          n_pulses, p, out["beams"].data_ptr(), out["centroid"].data_ptr(),
+                          out["beam_power"].data_ptr(), out["waveform"].data_ptr(),
+                          self._stream(stream))
+        return out
+
     def run(self, spec0, n_updates, t_fast=None, y=None, counters=None, stream=None,
             prepared=None):
         """Algorithm 1 and post-processing: U + 1 spectra, then Y.  The
@@ -638,6 +811,7 @@ class Batch:
         self.updates = [int(u) for _, _, u in members]
         self.ctx = sim_create(device, precision)
         self.batch = sim_batch_create(self.ctx, self.grids, self.radars, self.updates)
+        self.mode = SIM_BATCH_PERSISTENT          # the library's default
         nbytes = sim_batch_workspace_size(self.batch)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         sim_set_workspace(self.ctx, (self.workspace.data_ptr() + 255) & ~255, nbytes)
@@ -664,6 +838,11 @@ class Batch:
     def profile_read(self) -> dict:
         """{kernel kind: (summed ms, launches)} since profiling was enabled."""
         return sim_profile_read(self.ctx)
+
+    def set_mode(self, mode: int):
+        """SIM_BATCH_LANES or SIM_BATCH_PERSISTENT (sim_batch_set_mode)."""
+        sim_batch_set_mode(self.batch, mode)
+        self.mode = mode
 
     def empty_outputs(self):
         T = [self.torch.empty((u + 1, r.n_gates, r.n_doppler), dtype=self.complex_dtype,

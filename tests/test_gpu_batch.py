@@ -14,8 +14,12 @@ torch = pytest.importorskip("torch")
 
 def _members():
     # uneven grids, different sea states and window sizes
+    # three members share a shape (one persistent class, with different
+    # update counts: the class launch of update j holds only members with
+    # j <= U)
     spec = [(64, 64, 2.0, 8, 16, 16, 2, 1.5), (128, 32, 1.0, 16, 8, 8, 3, 2.5),
-            (32, 256, 2.0, 8, 32, 32, 1, 3.0)]
+            (32, 256, 2.0, 8, 32, 32, 1, 3.0), (64, 64, 2.0, 8, 16, 16, 4, 2.0),
+            (64, 64, 2.0, 8, 16, 16, 1, 1.0)]
     out = []
     for i, (nx, ny, d, G, N, nf, U, swh) in enumerate(spec):
         wl = workloads.tiny(nx=nx, ny=ny, spacing=d, n_gates=G, n_doppler=N, n_fast=nf,
@@ -30,14 +34,19 @@ def _spec(wl):
                                wl.sea.seed)
 
 
+MODES = [1, 2]      # SIM_BATCH_LANES, SIM_BATCH_PERSISTENT
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec,pcode,cdt,tol", [("fp64", 0, np.complex128, 1e-9),
                                                 ("fp32", 1, np.complex64, 5e-3)])
-def test_batch_matches_single_runs_and_oracle(prec, pcode, cdt, tol):
+def test_batch_matches_single_runs_and_oracle(prec, pcode, cdt, tol, mode):
     from paper_2408_11472_amd import simradar
-    print_case("batch", prec)
+    print_case("batch", prec, "mode", mode)
     wls = _members()
     specs_np = [_spec(w) for w in wls]
     batch = simradar.Batch([(w.grid, w.radar, w.n_updates) for w in wls], pcode)
+    batch.set_mode(mode)
     specs = [torch.as_tensor(s.astype(cdt), device="cuda") for s in specs_np]
     T, Y = batch.empty_outputs()
     batch.run(specs, T, Y, use_graph=False)
@@ -56,12 +65,14 @@ def test_batch_matches_single_runs_and_oracle(prec, pcode, cdt, tol):
     batch.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec,pcode,cdt", [("fp64", 0, np.complex128), ("fp32", 1, np.complex64)])
-def test_graph_replays_match_eager(prec, pcode, cdt):
+def test_graph_replays_match_eager(prec, pcode, cdt, mode):
     from paper_2408_11472_amd import simradar
-    print_case("graph", prec)
+    print_case("graph", prec, "mode", mode)
     wls = _members()
     batch = simradar.Batch([(w.grid, w.radar, w.n_updates) for w in wls], pcode)
+    batch.set_mode(mode)
     specs = [torch.as_tensor(_spec(w).astype(cdt), device="cuda") for w in wls]
     T, Y = batch.empty_outputs()
     batch.run(specs, T, Y, use_graph=False)
@@ -143,3 +154,32 @@ def test_row_paths_agree(prec, pcode, cdt, which):
     assert rel_l2(Tf, Ts) <= (1e-12 if prec == "fp64" else 1e-5 + 3 * np.sqrt(2 * n_diff / cf.size))
     assert int(nf[:5].sum()) == int(ns[:5].sum()) == wl.n_facets
     sim.close()
+
+
+@pytest.mark.parametrize("prec,pcode,cdt", [("fp64", 0, np.complex128), ("fp32", 1, np.complex64)])
+def test_persistent_mode_equals_lanes_mode_on_new_buffers(prec, pcode, cdt):
+    """Both batch modes on one batch object, then the persistent mode again
+    on another set of output buffers (its descriptors are rebuilt)."""
+    from paper_2408_11472_amd import simradar
+    print_case("batch modes", prec)
+    wls = _members()
+    batch = simradar.Batch([(w.grid, w.radar, w.n_updates) for w in wls], pcode)
+    specs = [torch.as_tensor(_spec(w).astype(cdt), device="cuda") for w in wls]
+    out = {}
+    for mode in (simradar.SIM_BATCH_LANES, simradar.SIM_BATCH_PERSISTENT,
+                 simradar.SIM_BATCH_PERSISTENT):
+        batch.set_mode(mode)
+        T, Y = batch.empty_outputs()
+        batch.run(specs, T, Y)
+        torch.cuda.synchronize()
+        out.setdefault(mode, []).append(([t.cpu().numpy() for t in T],
+                                         [y.cpu().numpy() for y in Y]))
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    ref_T, ref_Y = out[simradar.SIM_BATCH_LANES][0]
+    for T, Y in out[simradar.SIM_BATCH_PERSISTENT]:
+        for a, b in zip(T + Y, ref_T + ref_Y):
+            assert rel_l2(a, b) <= tol
+    with pytest.raises(simradar.SimError):
+        batch.set_mode(7)
+    batch.close()
+
