@@ -80,8 +80,8 @@ def parse():
                    help="skip the stress and batched sub-objects of the default line")
     p.add_argument("--extra-steps", type=int, default=2,
                    help="timed steps of the stress and batched workloads in the default line")
-    p.add_argument("--autotune", action="store_true",
-                   help="time the row paths and band counts first and run the fastest")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="skip the autotuner (row path and band count per shape, batch mode)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="before timing, copy a buffer of this size once (a plain copy kernel "
                         "of known traffic, to scale the HBM byte counters of a profiler run)")
@@ -215,6 +215,40 @@ def cpu_baseline(spec, wl):
                       f"wall including worker start-up; single core: one spectrum in {t1:.1f} s"}
 
 
+def run_delay_doppler(sim, Y, torch, burst=64, reps=20):
+    """Delay-Doppler processing (bursts of 64 pulses, centroid estimated per
+    burst, range migration corrected, multi-look) of the step's IQ: time per
+    call (HIP events on the launch stream), the HBM bytes it must move (the
+    IQ read twice, the beams written and read back by the range pass and read
+    by the multi-look) and the waveform against the oracle on the same IQ."""
+    import numpy as np
+    import oracle.delay_doppler as odd
+    st = torch.cuda.current_stream()
+    out = sim.delay_doppler(Y, burst=burst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        out = sim.delay_doppler(Y, burst=burst)
+    e1.record(st)
+    e1.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    nb = Y.shape[0] // burst
+    cs = Y.element_size()
+    moved = 2 * Y.numel() * cs + 4 * nb * burst * Y.shape[1] * cs
+    _, w_ref = odd.delay_doppler(Y.cpu().numpy().astype(np.complex128), sim_radar_view(sim),
+                                 burst=burst, centroid=None, migration=True)
+    err = float(np.linalg.norm(out["waveform"].cpu().numpy() - w_ref) / np.linalg.norm(w_ref))
+    return {"burst": burst, "bursts": nb, "ms_per_call": round(s * 1e3, 4),
+            "bytes_per_call": moved, "achieved_gbs": round(moved / s / 1e9, 1),
+            "waveform_rel_l2_vs_oracle": err}
+
+
+def sim_radar_view(sim):
+    """The context's radar as the oracle reads it (attribute access)."""
+    r = sim.radar
+    return type("Radar", (), {k: getattr(r, k) for k, _ in r._fields_})()
+
+
 def run_batch(a, members, steps, warmup, torch):
     """The batched-realisations workload: all members on one context, replayed
     as one captured HIP graph per step (FP32 + FP64 phase)."""
@@ -230,6 +264,10 @@ def run_batch(a, members, steps, warmup, torch):
     batch = simradar.Batch([(w.grid, w.radar, w.n_updates) for w in members],
                            simradar.SIM_PREC_FP32_PHASE64)
     T, Y = batch.empty_outputs()
+    tuning = None
+    if not a.no_autotune:
+        from paper_2408_11472_amd import autotune
+        tuning = autotune.tune_batch(batch, specs, T, Y, repeats=1)
     batch.run(specs, T, Y, use_graph=False)
     torch.cuda.synchronize()
     batch.profile(True)
@@ -254,6 +292,8 @@ def run_batch(a, members, steps, warmup, torch):
            "value": round(fu * steps / dt, 1), "unit": "facet-updates/s",
            "iq_pulses_per_s": round(pulses * steps / dt, 1),
            "roofline": path_roofline(ALG_BYTES_PER_FACET_UPDATE, fu * steps, dt),
+           "mode": "persistent" if getattr(batch, "mode", 2) == 2 else "lanes",
+           "tuning": tuning,
            "eager_kernels_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
     batch.close()
     del specs, T, Y
@@ -283,7 +323,7 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
             raise
         spec_t = torch.as_tensor(spec.astype(cdt), device="cuda")
         tuning = None
-        if a.autotune:
+        if not a.no_autotune:
             from paper_2408_11472_amd import autotune
             tuning = autotune.tune(sim, spec_t, use_cache=False)
         dt, dt_ev, dt_prof, prof, T, Y, prep = timed_steps(sim, spec_t, wl, steps, warmup, torch)
@@ -304,6 +344,8 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
                      "traffic_unit": "HBM bytes per update (rocprofv3 counters)",
                      "alg_bytes_per_update": ALG_BYTES_PER_FACET_UPDATE * scale * wl.n_facets,
                      "dominant_kernel": dominant_kernel(prof, wl, scale, measured_ok, name)})
+        dd = (run_delay_doppler(sim, Y, torch)
+              if name == "fp32" and wl.name.startswith("track_4096") else None)
         # one more update with per-facet codes (outside the timed region)
         code = torch.empty((g.ny, g.nx), dtype=torch.int32, device="cuda")
         cnt = sim.counters()
@@ -325,6 +367,7 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
             "roofline": roof,
             "finite": bool(torch.isfinite(torch.view_as_real(Y)).all().item()),
             "tuning": tuning,
+            "delay_doppler": dd,
         }
         print(f"[bench] {wl.name} {name}: {ms_step:.2f} ms/step  "
               f"{results[name]['facet_updates_per_s']:.3e} facet-updates/s  "
@@ -372,6 +415,18 @@ def main():
     if a.workload == "gradient_2048":
         main_gradient(a, workloads.gradient_2048())
         return
+    if a.workload == "nfast_sweep":
+        out = run_nfast_sweep(torch, with_iq=True)
+        line = {"metric": METRIC, "value": out["regular"]["facet_updates_per_s"],
+                "unit": "facet-updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+                "ms_per_step": round(out["regular"]["gpu_s"] * 1e3, 3),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32", "data": "synthetic",
+                "config": {"workload": out["workload"], "range_phase": "f64",
+                           "parallelism": "single-gpu"},
+                "nfast_sweep": out}
+        print(json.dumps(line), flush=True)
+        return
 
     if a.copy_calibration_mib > 0:
         n = a.copy_calibration_mib * 1024 * 1024 // 4
@@ -412,6 +467,7 @@ def main():
         "roofline": r32["roofline"],
         "copy_bandwidth": copy,
         "tuning": r32["tuning"],
+        "delay_doppler": r32["delay_doppler"],
     }
     if "fp64" in results:
         r64 = results["fp64"]
@@ -438,6 +494,7 @@ def main():
             "kernels_ms_per_step": s32["kernels_ms_per_step"],
             "roofline": {k: v for k, v in s32["roofline"].items() if k != "traffic"}}
         line["batched_16"] = run_batch(a, workloads.batched_16(), max(2, a.extra_steps), 1, torch)
+        line["nfast_sweep"] = run_nfast_sweep(torch)
     # The paper gives only end-to-end wall times of its own scenario (Sec. IV:
     # 3.51e8 scatterers, 267379 pulses) on 4 GTX 1080; the rate they imply for
     # the fast mode at n_fast = 250 is quoted as context, not as a target.
@@ -447,6 +504,26 @@ def main():
     if cpu_line is not None:
         line["cpu_baseline"] = cpu_line
     print(json.dumps(line), flush=True)
+
+
+def run_nfast_sweep(torch, with_iq=False, nx=1024, n_pulses=5000):
+    """Regular mode (a surface update at every pulse) and the fast mode at
+    n_fast = 250 .. 1250 on one 1024^2-facet scene of 6.25 m^2 scatterers
+    (wind sea + 4 m swell, CWM on), 5000 pulses, FP32 with double range and
+    phase: GPU time and speed-up per mode (the paper's Fig. 4) and the
+    fidelity of each fast-mode multi-look waveform against the regular mode's
+    (the paper's Fig. 6), in units of the speckle standard deviation."""
+    from paper_2408_11472_amd import nfast, simradar
+    scene = nfast.sweep_scene(nx=nx, n_pulses=n_pulses)
+    res = nfast.sweep(scene, nfast.SWEEP_NFAST, simradar.SIM_PREC_FP32_PHASE64, torch,
+                      with_iq=with_iq)
+    reg = res[1]
+
+    def clean(r):
+        return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+    return {"workload": scene.name, "facets": scene.n_facets, "pulses": scene.n_pulses,
+            "regular": clean(reg),
+            "fast": [clean(res[nf]) for nf in nfast.SWEEP_NFAST]}
 
 
 def main_gradient(a, wl):

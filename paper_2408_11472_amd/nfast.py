@@ -139,18 +139,40 @@ def iq_correlation(Y, max_lag):
                      for k in range(max_lag + 1)])
 
 
+# Mean over a segment of (sqrt(1 - tau) + sqrt(tau))^2 = 1 + pi/4: the power
+# gain of the eq. (1) cross-fade when the long-time signals of two
+# consecutive spectra are fully coherent (eq. (1) conserves the variance of
+# independent signals only).
+COHERENT_POWER_GAIN = 1.0 + np.pi / 4.0
+
+
+def _normalized(p, s):
+    """Waveform normalised to unit sum and the standard deviation of each
+    normalised gate (first order in the per-gate deviations, gates taken as
+    independent)."""
+    S = p.sum()
+    q = p / S
+    var = (s / S) ** 2 * (1.0 - 2.0 * q) + q ** 2 * np.sum((s / S) ** 2)
+    return q, np.sqrt(np.maximum(var, 0.0))
+
+
 def compare_waveforms(Y_fast, Y_reg, gate_floor=0.01):
     """Fidelity of a fast-mode run against the regular mode over the same
-    pulses: per-gate waveform difference in units of the combined speckle
+    pulses.  The waveforms are compared as the paper's Fig. 6 does, normalised
+    (unit sum here): per-gate difference in units of the combined speckle
     standard deviation (the two runs see one surface, so their speckle is
     positively correlated and this is conservative), over the gates holding
-    at least gate_floor of the peak power; relative L2 difference of the
-    waveforms; total-power ratio with its standard deviation."""
+    at least gate_floor of the peak power, and the relative L2 difference of
+    the normalised waveforms.  The total-power ratio is reported with its
+    standard deviation; eq. (1) keeps it at 1 for independent consecutive
+    signals and raises it up to 1 + pi/4 for coherent ones."""
     pf, sf, tf = mean_and_sigma(np.abs(np.asarray(Y_fast)) ** 2)
     pr, sr, tr = mean_and_sigma(np.abs(np.asarray(Y_reg)) ** 2)
-    sig = np.sqrt(sf ** 2 + sr ** 2)
+    qf, uf = _normalized(pf, sf)
+    qr, ur = _normalized(pr, sr)
+    sig = np.sqrt(uf ** 2 + ur ** 2)
     keep = pr >= gate_floor * pr.max()
-    z = np.where(keep & (sig > 0), (pf - pr) / np.where(sig > 0, sig, 1.0), 0.0)
+    z = np.where(keep & (sig > 0), (qf - qr) / np.where(sig > 0, sig, 1.0), 0.0)
     tot_f, tot_r = pf.sum(), pr.sum()
     # total power: the per-gate means are correlated across gates as well;
     # bound its deviation by the sum of the per-gate deviations
@@ -159,7 +181,7 @@ def compare_waveforms(Y_fast, Y_reg, gate_floor=0.01):
         "waveform_fast": pf, "waveform_regular": pr,
         "z": z, "max_abs_z": float(np.max(np.abs(z))), "gates_compared": int(keep.sum()),
         "rms_z": float(np.sqrt(np.mean(z[keep] ** 2))) if keep.any() else 0.0,
-        "waveform_rel_l2": float(np.linalg.norm(pf - pr) / np.linalg.norm(pr)),
+        "waveform_rel_l2": float(np.linalg.norm(qf - qr) / np.linalg.norm(qr)),
         "power_ratio": float(tot_f / tot_r), "power_ratio_sigma": float(s_tot / tot_r),
         "tau_fast_median": float(np.median(tf[keep])) if keep.any() else 0.0,
         "tau_regular_median": float(np.median(tr[keep])) if keep.any() else 0.0,

@@ -21,7 +21,8 @@ import oracle.scatter as osc
 import oracle.surface as osurf
 from paper_2408_11472_amd import inputs, workloads
 from tests.gpu_helpers import (continuous_coordinates, expected_flips, explain_mismatches,
-                               print_case, rel_l2, rounded_facets, to_torch_facets)
+                               print_case, print_precision, rel_l2, rounded_facets,
+                               to_torch_facets)
 
 pytestmark = pytest.mark.gpu
 
@@ -277,8 +278,17 @@ def test_full_run_small_256(prec, pcode, npdt):
     T, Y = sim.run(spec_t, wl.n_updates)
     torch.cuda.synchronize()
     T_ref, Y_ref = ofm.simulate(spec, wl.grid, wl.radar, wl.n_updates)
-    assert rel_l2(T.cpu().numpy(), T_ref) <= (1e-9 if prec == "fp64" else 5e-3)
-    assert rel_l2(Y.cpu().numpy(), Y_ref) <= (1e-9 if prec == "fp64" else 5e-3)
+    eT, eY = rel_l2(T.cpu().numpy(), T_ref), rel_l2(Y.cpu().numpy(), Y_ref)
+    # the multi-look waveform of the run (the GPU kernel) against the oracle's
+    import oracle.adjoint as oad
+    P, _ = sim.waveform_loss(Y)
+    torch.cuda.synchronize()
+    eP = rel_l2(P.cpu().numpy(), oad.waveform(Y_ref))
+    for name, v in (("T_fast", eT), ("Y", eY), ("P", eP)):
+        print_precision("small_256", f"{prec} end to end", name, v)
+    assert eT <= (1e-9 if prec == "fp64" else 5e-3)
+    assert eY <= (1e-9 if prec == "fp64" else 5e-3)
+    assert eP <= (1e-9 if prec == "fp64" else 1e-3)
     # the three-call path gives the same spectra as the fused call
     T3 = sim.empty_spectra(wl.n_spec)
     for j in range(wl.n_spec):

@@ -93,3 +93,24 @@ def test_mode_bins_and_pulses():
         # same track and range window as the regular mode
         assert m.radar.sat_y0 == scene.radar.sat_y0
         assert m.radar.window_start == scene.radar.window_start
+
+
+def test_coherent_power_gain_of_the_cross_fade():
+    """Eq. (1) keeps the variance of independent consecutive signals and
+    raises coherent ones by the segment mean of (sqrt(1 - tau) + sqrt(tau))^2
+    = 1 + pi/4 (the oracle's post-processing, a static scatterer in one
+    bin), which is the bound nfast.COHERENT_POWER_GAIN states."""
+    import oracle.iq as oiq
+    nf, U, G, N = 400, 6, 1, 1024
+    T = np.zeros((U + 1, G, N), complex)
+    T[:, 0, 0] = 0.8 - 0.3j
+    Y = oiq.segments_to_iq(T, nf)
+    gain = np.mean(np.abs(Y) ** 2) / abs(T[0, 0, 0]) ** 2
+    assert abs(gain - nfast.COHERENT_POWER_GAIN) < 2.0 / nf, gain
+    # independent spectra: the gain averages to 1
+    rng = np.random.default_rng(17)
+    T = rng.standard_normal((U + 1, 256, 64)) + 1j * rng.standard_normal((U + 1, 256, 64))
+    Y = oiq.segments_to_iq(T, 32)
+    s = oiq.long_time_signals(T)
+    gain = np.mean(np.abs(Y) ** 2) / np.mean(np.abs(s) ** 2)
+    assert abs(gain - 1.0) < 0.02, gain
