@@ -82,6 +82,9 @@ def parse():
                    help="timed steps of the stress and batched workloads in the default line")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the autotuner (row path and band count per shape, batch mode)")
+    p.add_argument("--tuning-cache", action="store_true",
+                   help="take the autotuner's choice from its cache file when it has one "
+                        "(a profiled run then launches no candidate)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="before timing, copy a buffer of this size once (a plain copy kernel "
                         "of known traffic, to scale the HBM byte counters of a profiler run)")
@@ -325,7 +328,7 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
         tuning = None
         if not a.no_autotune:
             from paper_2408_11472_amd import autotune
-            tuning = autotune.tune(sim, spec_t, use_cache=False)
+            tuning = autotune.tune(sim, spec_t, use_cache=a.tuning_cache)
         dt, dt_ev, dt_prof, prof, T, Y, prep = timed_steps(sim, spec_t, wl, steps, warmup, torch)
         fu = wl.n_facets * wl.n_spec * steps
         ms_step = dt / steps * 1e3

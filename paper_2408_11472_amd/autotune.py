@@ -26,10 +26,12 @@ def cache_path() -> str:
 
 
 def shape_key(sim) -> str:
-    import torch
+    """Cache key of a shape: precision, grid sides, gates and bins.  The cache
+    file belongs to one machine (its path is per user or set by the caller);
+    the device name is left out because some runtimes (a profiler's) report
+    it empty."""
     g, r = sim.grid, sim.radar
-    dev = torch.cuda.get_device_name(sim.device)
-    return (f"{dev}|prec{sim.precision}|{g.nx}x{g.ny}|G{r.n_gates}|N{r.n_doppler}")
+    return f"prec{sim.precision}|{g.nx}x{g.ny}|G{r.n_gates}|N{r.n_doppler}"
 
 
 def _load():

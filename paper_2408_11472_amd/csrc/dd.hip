@@ -159,20 +159,31 @@ dd_range_kernel(cplx<Real>* __restrict__ Z, int G, int M, int FB, double mig,
   for (int i = threadIdx.x; i < nf * G; i += blockDim.x) zb[i] = cscale(R2[i], inv);
 }
 
-// beam_power[f][g] = mean over bursts of |Z[b][f][g]|^2 (double, bursts in
-// order); one thread per (f, g).
+// beam_power[f][g] = mean over bursts of |Z[b][f][g]|^2 (double).  A block
+// takes 64 cells (f, g); wave w of its four adds the bursts b = w mod 4 in
+// order, and the four partial sums are added in wave order, so the
+// association is fixed.
 template <typename Real>
 __global__ void __launch_bounds__(kDDThreads)
 dd_multilook_beams_kernel(const cplx<Real>* __restrict__ Z, int G, int M, int nb,
                           Real* __restrict__ beam_power) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M * G) return;
+  __shared__ double part[kDDThreads / 64][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    const cplx<Real> z = Z[(size_t)b * M * G + i];
-    acc += (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+  if (i < M * G) {
+    for (int b = w; b < nb; b += nw) {
+      const cplx<Real> z = Z[(size_t)b * M * G + i];
+      acc += (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+    }
   }
-  beam_power[i] = (Real)(acc / (double)nb);
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < M * G) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += part[k][lane];
+    beam_power[i] = (Real)(s / (double)nb);
+  }
 }
 
 // waveform[g] = mean over beams of beam_power[f][g] (double, beams in order).
@@ -215,7 +226,7 @@ hipError_t launch_delay_doppler(const void* y, int G, int M, int n_bursts, int c
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(dd_multilook_beams_kernel<Real>, dim3((M * G + kDDThreads - 1) / kDDThreads),
+  hipLaunchKernelGGL(dd_multilook_beams_kernel<Real>, dim3((M * G + 63) / 64),
                      dim3(kDDThreads), 0, st, (const cplx<Real>*)beams, G, M, n_bursts,
                      (Real*)beam_power);
   e = hipGetLastError();

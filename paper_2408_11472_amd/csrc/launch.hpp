@@ -25,9 +25,19 @@ __host__ __device__ constexpr size_t lpad_c(size_t i) { return i + (i >> 4); }
 // Column pass: CPB adjacent columns per block, ny/16 threads per column,
 // as many columns as fit kColLds of LDS (one column at least).
 constexpr size_t kColLds = kLdsBudget;
+// Short columns (ny <= kColSmallNy) get blocks of at most kColSmallThreads
+// threads, so that grids of 1024^2 and 2048^2 still launch hundreds of blocks
+// (measured: the 1024^2 regular-mode run 532 -> 461 ms, the 2048^2 gradient
+// step 3.13 -> 3.02 ms; 256 threads was slower on 2048^2).
+#ifndef SIMK_COL_SMALL_THREADS
+#define SIMK_COL_SMALL_THREADS 512
+#endif
+constexpr int kColSmallThreads = SIMK_COL_SMALL_THREADS;
+constexpr int kColSmallNy = 2048;
 __host__ __device__ constexpr int col_cpb(int log2ny, int cs) {
+  const int cap = (1 << log2ny) <= kColSmallNy ? kColSmallThreads : 1024;
   int cpb = 16;
-  while (cpb > 1 && ((long)cpb * ((1 << log2ny) / 16) > 1024 ||
+  while (cpb > 1 && ((long)cpb * ((1 << log2ny) / 16) > cap ||
                      (size_t)cpb * lpad_c((size_t)1 << log2ny) * cs > kColLds))
     cpb >>= 1;
   return cpb;
