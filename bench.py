@@ -49,11 +49,11 @@ LAYOUT_SHARE = {"surface_colpass": 8 + 32, "surface_rowpass": 32, "fused_rowpass
 # they were taken on.
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "b0be18267d4431c3",
-    "fp32": {"surface_colpass": 823e6, "surface_rowpass": 1141e6, "accumulate_facets": 606e6,
-             "reduce_partials": 3e6},
-    "fp64": {"surface_colpass": 1345e6, "surface_rowpass": 2283e6, "accumulate_facets": 1210e6,
-             "reduce_partials": 4e6},
+    "source_sha": "db00451ed9060564",
+    "fp32": {"surface_colpass": 828e6, "surface_rowpass": 1141e6,
+             "accumulate_facets": 607e6, "reduce_partials": 3e6},
+    "fp64": {"surface_colpass": 1345e6, "surface_rowpass": 2283e6,
+             "accumulate_facets": 1211e6, "reduce_partials": 3e6},
 }
 PER_UPDATE_KERNELS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
                       "reduce_partials")

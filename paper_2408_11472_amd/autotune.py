@@ -5,8 +5,9 @@ For one (grid, radar, precision) it times the fused update+accumulate call
 on each row path (fused row pass with each candidate band count, i.e. the
 number of LDS windows and row-pass blocks per update; or the split facet
 row pass + facet accumulate) using the library's HIP-event timing, keeps the
-fastest, and caches it in a JSON file keyed by the device name and the
-shape.  Cache: $SIMRADAR_TUNING_CACHE or ~/.cache/simradar/tuning.json.
+fastest (the split path on a tie within FUSED_MARGIN), and caches it in a
+JSON file keyed by the shape.  Cache: $SIMRADAR_TUNING_CACHE or
+~/.cache/simradar/tuning.json.
 """
 from __future__ import annotations
 
@@ -16,6 +17,10 @@ import os
 CANDIDATE_BANDS = (64, 128, 256, 512)
 # (row path, band count) pairs timed; the split path has no band count
 PATH_FUSED, PATH_SPLIT = 1, 2
+# The fused row pass is kept only when it beats the split path by more than
+# this fraction: within it the two are a tie (timing noise decides), and the
+# split path, whose kernels are timed one by one, is the stable choice.
+FUSED_MARGIN = 0.02
 
 
 def cache_path() -> str:
@@ -56,6 +61,17 @@ def _apply(sim, entry):
     sim.set_row_bands(entry["row_bands"])
 
 
+def pick(times: dict) -> tuple:
+    """The (row path, band count) to use from the times per update of every
+    candidate: the fastest, except that a fused candidate must beat the split
+    path by more than FUSED_MARGIN."""
+    best = min(times, key=times.get)
+    split = times.get((PATH_SPLIT, 0))
+    if best[0] == PATH_FUSED and split is not None and split <= times[best] * (1 + FUSED_MARGIN):
+        return (PATH_SPLIT, 0)
+    return best
+
+
 def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
     """Pick the row path and the band count of the fused row pass for this
     simulator's shape and apply them.  Returns {"row_path": p, "row_bands": n,
@@ -82,7 +98,7 @@ def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
         sim.profile(False)
         total = sum(ms for ms, n in prof.values())
         times[(path, nb)] = 1e3 * total / repeats
-    best = min(times, key=times.get)
+    best = pick(times)
     entry = {"row_path": best[0], "row_bands": best[1],
              "times_us": {("fused%d" % nb if p == PATH_FUSED else "split"): round(v, 1)
                           for (p, nb), v in times.items()}}
