@@ -328,7 +328,8 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
         tuning = None
         if not a.no_autotune:
             from paper_2408_11472_amd import autotune
-            tuning = autotune.tune(sim, spec_t, use_cache=a.tuning_cache)
+            tuning = autotune.tune(sim, spec_t, use_cache=a.tuning_cache,
+                                   run_times=[wl.update_time(j) for j in range(wl.n_spec)])
         dt, dt_ev, dt_prof, prof, T, Y, prep = timed_steps(sim, spec_t, wl, steps, warmup, torch)
         fu = wl.n_facets * wl.n_spec * steps
         ms_step = dt / steps * 1e3
@@ -419,7 +420,7 @@ def main():
         main_gradient(a, workloads.gradient_2048())
         return
     if a.workload == "nfast_sweep":
-        out = run_nfast_sweep(torch, with_iq=True)
+        out = run_nfast_sweep(torch, with_iq=True, tune=not a.no_autotune)
         line = {"metric": METRIC, "value": out["regular"]["facet_updates_per_s"],
                 "unit": "facet-updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
                 "ms_per_step": round(out["regular"]["gpu_s"] * 1e3, 3),
@@ -497,7 +498,7 @@ def main():
             "kernels_ms_per_step": s32["kernels_ms_per_step"],
             "roofline": {k: v for k, v in s32["roofline"].items() if k != "traffic"}}
         line["batched_16"] = run_batch(a, workloads.batched_16(), max(2, a.extra_steps), 1, torch)
-        line["nfast_sweep"] = run_nfast_sweep(torch)
+        line["nfast_sweep"] = run_nfast_sweep(torch, tune=not a.no_autotune)
     # The paper gives only end-to-end wall times of its own scenario (Sec. IV:
     # 3.51e8 scatterers, 267379 pulses) on 4 GTX 1080; the rate they imply for
     # the fast mode at n_fast = 250 is quoted as context, not as a target.
@@ -509,7 +510,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_nfast_sweep(torch, with_iq=False, nx=1024, n_pulses=5000):
+def run_nfast_sweep(torch, with_iq=False, nx=1024, n_pulses=5000, tune=True):
     """Regular mode (a surface update at every pulse) and the fast mode at
     n_fast = 250 .. 1250 on one 1024^2-facet scene of 6.25 m^2 scatterers
     (wind sea + 4 m swell, CWM on), 5000 pulses, FP32 with double range and
@@ -519,7 +520,7 @@ def run_nfast_sweep(torch, with_iq=False, nx=1024, n_pulses=5000):
     from paper_2408_11472_amd import nfast, simradar
     scene = nfast.sweep_scene(nx=nx, n_pulses=n_pulses)
     res = nfast.sweep(scene, nfast.SWEEP_NFAST, simradar.SIM_PREC_FP32_PHASE64, torch,
-                      with_iq=with_iq)
+                      with_iq=with_iq, tune=tune)
     reg = res[1]
 
     def clean(r):

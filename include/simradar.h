@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 4
+#define SIM_ABI_VERSION 5
 
 typedef enum sim_status {
   SIM_OK = 0,
@@ -249,6 +249,26 @@ sim_status sim_update_and_accumulate_prepared(sim_ctx *ctx, const sim_grid *grid
                                               double t, int32_t j, void *t_fast,
                                               int32_t n_spec, sim_counters *counters,
                                               int32_t *facet_code, void *stream);
+
+/* The updates of Algorithm 1's loop over spectra (the spectra are
+ * independent given the initial spectrum) in one call: for i in [0, count),
+ * sim_update_and_accumulate_prepared of spectrum j0 + i at time times[i]
+ * (same launches; same results up to the summation order of the window
+ * atomics).  With SIM_TUNE_UPDATE_LANES = L > 1 update j0 + i runs on lane
+ * i mod L with that lane's workspace slice; the lanes are forked from
+ * `stream` and joined back to it, so the call stays ordered on `stream`
+ * (and can be captured).  On small grids an update is a chain of short
+ * dependent launches that leaves much of the GPU idle; lanes overlap them.
+ *   times     host array of count pulse times [s], read during the call.
+ *   t_fast    [n_spec][n_gates][n_doppler] complex, accumulated; needs
+ *             0 <= j0 and j0 + count <= n_spec.
+ *   counters  device sim_counters, accumulated over the updates; may be NULL.
+ * Arguments are checked before anything is launched (every time must be
+ * finite); a launch error stops the loop and is returned. */
+sim_status sim_run_updates(sim_ctx *ctx, const sim_grid *grid, const void *prepared,
+                           const sim_radar *radar, int32_t j0, int32_t count,
+                           const double *times, void *t_fast, int32_t n_spec,
+                           sim_counters *counters, void *stream);
 
 /* Post-processing of Sec. III.B: s_j[g][m] = sum_k T[j][g][k]
  * exp(+2 pi i k m / N) (unnormalised), then for every pulse x in
@@ -470,6 +490,14 @@ sim_status sim_streamer_run(sim_streamer *streamer, const sim_grid *grid, const 
 #define SIM_ROW_PATH_AUTO 0       /*   the faster on MI355X: currently the split path        */
 #define SIM_ROW_PATH_FUSED 1      /*   fused row pass: facets stay on chip                    */
 #define SIM_ROW_PATH_SPLIT 2      /*   facet row pass into the workspace, then facet accumulate */
+#define SIM_TUNE_UPDATE_LANES 2   /* streams sim_run_updates deals the updates to, 1 .. 4:      */
+                                  /*   lane 0 is the caller's stream, the others the context's */
+                                  /*   own (made here, default priority); each lane needs a    */
+                                  /*   workspace of its own, so sim_workspace_size returns     */
+                                  /*   lanes x the one-lane size: set the lanes first, then    */
+                                  /*   size and set the workspace.  Short updates (small grids) */
+                                  /*   then overlap; per-kernel times (sim_profile_*) of       */
+                                  /*   overlapping launches include each other's share.        */
 sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 
 /* ---- per-kernel timing (profiling aid) ----------------------------------

@@ -5,8 +5,10 @@ For one (grid, radar, precision) it times the fused update+accumulate call
 on each row path (fused row pass with each candidate band count, i.e. the
 number of LDS windows and row-pass blocks per update; or the split facet
 row pass + facet accumulate) using the library's HIP-event timing, keeps the
-fastest (the split path on a tie within FUSED_MARGIN), and caches it in a
-JSON file keyed by the shape.  Cache: $SIMRADAR_TUNING_CACHE or
+fastest (the split path on a tie within FUSED_MARGIN); then it times a short
+run of updates (sim_run_updates) on 1 to 4 update lanes and keeps the
+fastest (fewer lanes on a tie within LANES_MARGIN).  The choice is cached in
+a JSON file keyed by the shape.  Cache: $SIMRADAR_TUNING_CACHE or
 ~/.cache/simradar/tuning.json.
 """
 from __future__ import annotations
@@ -21,6 +23,13 @@ PATH_FUSED, PATH_SPLIT = 1, 2
 # this fraction: within it the two are a tie (timing noise decides), and the
 # split path, whose kernels are timed one by one, is the stable choice.
 FUSED_MARGIN = 0.02
+CANDIDATE_LANES = (1, 2, 3, 4)
+# More lanes are kept only when they beat fewer by more than this fraction.
+# The tuner's short runs overstate the gain of lanes on large grids against a
+# whole run (measured, 3 lanes against 1: 4096^2 track 7.5 % in the tuner,
+# 6 % over the run; 8192 x 16384 stress 3 % in the tuner, 0.6 % slower over
+# the run of 513 updates), so the margin is set between the two.
+LANES_MARGIN = 0.04
 
 
 def cache_path() -> str:
@@ -59,6 +68,7 @@ def _store(cache):
 def _apply(sim, entry):
     sim.set_row_path(entry["row_path"])
     sim.set_row_bands(entry["row_bands"])
+    sim.set_update_lanes(entry.get("update_lanes", 1))
 
 
 def pick(times: dict) -> tuple:
@@ -72,14 +82,75 @@ def pick(times: dict) -> tuple:
     return best
 
 
-def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
+def pick_lanes(times: dict) -> int:
+    """The lane count to use from the run time of each candidate: the
+    fastest, unless fewer lanes are within LANES_MARGIN of it."""
+    best = min(times, key=times.get)
+    for n in sorted(times):
+        if n < best and times[n] <= times[best] * (1 + LANES_MARGIN):
+            return n
+    return best
+
+
+def lane_run_updates(sim) -> int:
+    """Updates per timed run of the lane tuning: about 4e8 facet-updates,
+    between 24 and 192."""
+    g = sim.grid
+    return int(max(24, min(192, 4e8 // (g.nx * g.ny))))
+
+
+def sample_times(times, n: int) -> list:
+    """n of the run's update times, evenly spaced over the whole run (the
+    first updates of a long track may light little of the grid, and an
+    update's cost depends on how many facets it scatters)."""
+    times = list(times)
+    if len(times) <= n:
+        return times
+    return [times[(i * (len(times) - 1)) // (n - 1)] for i in range(n)]
+
+
+def tune_lanes(sim, spec0, repeats: int = 3, times=None) -> dict:
+    """Time a run of updates on each candidate lane count (HIP events on the
+    launch stream, best of `repeats`); returns {lanes: ms}.  times: the
+    run's update times (sampled evenly); default: the first updates at
+    j n_fast / PRF."""
+    import torch
+    r = sim.radar
+    n = lane_run_updates(sim)
+    if times is None:
+        times = [(j * r.n_fast) / r.prf_hz for j in range(n)]
+    times = sample_times(times, n)
+    n = len(times)
+    prep = sim.prepare_spectrum(spec0)
+    T = sim.empty_spectra(n)
+    out = {}
+    for lanes in CANDIDATE_LANES:
+        sim.set_update_lanes(lanes)
+        sim.run_updates(prep, times, 0, T)                   # warm-up
+        best = None
+        for _ in range(repeats):
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            sim.run_updates(prep, times, 0, T)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[lanes] = best
+    return out
+
+
+def tune(sim, spec0, repeats: int = 6, use_cache: bool = True, run_times=None) -> dict:
     """Pick the row path and the band count of the fused row pass for this
-    simulator's shape and apply them.  Returns {"row_path": p, "row_bands": n,
-    "times_us": {...}} (times per update of every candidate)."""
+    simulator's shape, then the update lanes (on the run's update times
+    `run_times` when given), and apply them.  Returns {"row_path": p, "row_bands": n,
+    "times_us": {...}, "update_lanes": l, "lanes_ms": {...}} (times per update
+    of every row path candidate, run times of every lane count)."""
     import torch
     key = shape_key(sim)
     cache = _load() if use_cache else {}
-    if key in cache and "row_path" in cache[key]:
+    if key in cache and "row_path" in cache[key] and "update_lanes" in cache[key]:
         _apply(sim, cache[key])
         return cache[key]
     T = sim.empty_spectra(2)
@@ -99,9 +170,15 @@ def tune(sim, spec0, repeats: int = 6, use_cache: bool = True) -> dict:
         total = sum(ms for ms, n in prof.values())
         times[(path, nb)] = 1e3 * total / repeats
     best = pick(times)
+    sim.set_row_path(best[0])
+    sim.set_row_bands(best[1])
+    lane_ms = tune_lanes(sim, spec0, times=run_times)
     entry = {"row_path": best[0], "row_bands": best[1],
              "times_us": {("fused%d" % nb if p == PATH_FUSED else "split"): round(v, 1)
-                          for (p, nb), v in times.items()}}
+                          for (p, nb), v in times.items()},
+             "update_lanes": pick_lanes(lane_ms),
+             "lanes_ms": {str(k): round(v, 3) for k, v in lane_ms.items()},
+             "lanes_updates": lane_run_updates(sim)}
     _apply(sim, entry)
     if use_cache:
         cache = _load()

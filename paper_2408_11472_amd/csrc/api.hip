@@ -38,6 +38,12 @@ struct sim_ctx {
   size_t used;                  // pairs recorded
   uint64_t dropped;             // launches not timed (pool exhausted)
   int tab_slot;                 // slot of the look-up tables (-1: closed forms)
+  // update lanes of sim_run_updates (SIM_TUNE_UPDATE_LANES): lane 0 is the
+  // caller's stream, lanes 1.. have their own streams (default priority);
+  // each lane has its own workspace slice
+  int lanes;
+  std::vector<hipStream_t> lane_st;
+  std::vector<hipEvent_t> lane_ev;   // [0]: fork, [1 + l]: join of stream l
 };
 
 // Twiddle tables (entries [M, 2M) hold e^{+2 pi i m / M} for every power of
@@ -75,6 +81,7 @@ using simk::kLdsBudget;
 constexpr size_t kWindowBudget = 32 * 1024;    // LDS of one window of partial spectra
 constexpr int kSlots = 4;                      // window slots per band
 constexpr int kMaxBands = 512;       // bands (blocks) of the fused row pass
+constexpr int kMaxUpdateLanes = 4;   // update lanes of sim_run_updates
 constexpr int kAccBands = 512;       // bands (blocks) of the facet accumulate
 constexpr int kWsBands = kAccBands > kMaxBands ? kAccBands : kMaxBands;
 constexpr int kProfilePairs = 8192;  // timed launches per profile record
@@ -342,6 +349,19 @@ void release_tab_slot(sim_ctx* c) {
   c->tab_slot = -1;
 }
 
+// The lane streams and events (after the work queued on them).
+void release_lanes(sim_ctx* c) {
+  if (!c->lane_st.empty() || !c->lane_ev.empty()) (void)use_device(c);
+  for (hipStream_t st : c->lane_st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t e : c->lane_ev) (void)hipEventDestroy(e);
+  c->lane_st.clear();
+  c->lane_ev.clear();
+  c->lanes = 1;
+}
+
 bool facets_ok(const sim_facets* f) {
   if (!f) return false;
   void* const p[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
@@ -594,6 +614,7 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->row_path = SIM_ROW_PATH_AUTO;
   c->capturing = false;
   c->tab_slot = -1;
+  c->lanes = 1;
   *ctx = c;
   return SIM_OK;
 }
@@ -602,6 +623,7 @@ sim_status sim_destroy(sim_ctx* ctx) {
   if (!ctx) return SIM_OK;
   release_tab_slot(ctx);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  release_lanes(ctx);
   delete ctx;
   return SIM_OK;
 }
@@ -620,7 +642,8 @@ sim_status sim_workspace_size(const sim_ctx* ctx, const sim_grid* grid, const si
   s = check_radar(radar);
   if (s != SIM_OK) return s;
   if (window_bins(radar->n_gates, radar->n_doppler, csize(ctx), 0) < 1) return SIM_ERR_UNSUPPORTED;
-  *bytes = ws_layout(grid, radar, csize(ctx)).total;
+  const size_t one = ws_layout(grid, radar, csize(ctx)).total;
+  *bytes = ctx->lanes > 1 ? (size_t)ctx->lanes * align256(one) : one;
   return SIM_OK;
 }
 
@@ -802,6 +825,58 @@ sim_status sim_update_and_accumulate_prepared(sim_ctx* ctx, const sim_grid* grid
                                               void* stream) {
   return update_and_accumulate_impl(ctx, grid, prepared, true, radar, t, j, t_fast, n_spec,
                                     counters, facet_code, stream);
+}
+
+sim_status sim_run_updates(sim_ctx* ctx, const sim_grid* grid, const void* prepared,
+                           const sim_radar* radar, int32_t j0, int32_t count,
+                           const double* times, void* t_fast, int32_t n_spec,
+                           sim_counters* counters, void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, radar, &L);
+  if (s != SIM_OK) return s;
+  if (!prepared || !t_fast || !times) return SIM_ERR_ARG;
+  if (count < 1 || j0 < 0 || n_spec < 1 || j0 > n_spec - count) return SIM_ERR_SHAPE;
+  for (int32_t i = 0; i < count; ++i)
+    if (!isfin(times[i])) return SIM_ERR_ARG;
+  const int NL = count > 1 ? std::min(ctx->lanes, (int)count) : 1;
+  if (NL == 1) {
+    for (int32_t i = 0; i < count && s == SIM_OK; ++i)
+      s = update_and_accumulate_impl(ctx, grid, prepared, true, radar, times[i], j0 + i, t_fast,
+                                     n_spec, counters, nullptr, stream);
+    return s;
+  }
+  // Lanes: update j0 + i runs on lane i mod NL (lane 0 the caller's stream)
+  // with that lane's workspace slice; the lanes are forked from the caller's
+  // stream and joined back to it, so the call is ordered on `stream` like
+  // the loop above (also under graph capture).  Updates write distinct
+  // spectra; the counters are added atomically.
+  const size_t slice = align256(L.total);
+  if (ctx->ws_bytes < (size_t)ctx->lanes * slice) return SIM_ERR_WORKSPACE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  s = dev(hipEventRecord(ctx->lane_ev[0], st));
+  for (int l = 1; l < NL && s == SIM_OK; ++l)
+    s = dev(hipStreamWaitEvent(ctx->lane_st[l - 1], ctx->lane_ev[0], 0));
+  if (s != SIM_OK) return s;
+  void* const ws0 = ctx->ws;
+  const size_t ws_bytes0 = ctx->ws_bytes;
+  ctx->ws_bytes = slice;
+  for (int32_t i = 0; i < count && s == SIM_OK; ++i) {
+    const int l = i % NL;
+    ctx->ws = (char*)ws0 + (size_t)l * slice;
+    s = update_and_accumulate_impl(ctx, grid, prepared, true, radar, times[i], j0 + i, t_fast,
+                                   n_spec, counters, nullptr, l ? ctx->lane_st[l - 1] : st);
+  }
+  ctx->ws = ws0;
+  ctx->ws_bytes = ws_bytes0;
+  // always join, so that a capture stays well formed
+  for (int l = 1; l < NL; ++l) {
+    sim_status sj = dev(hipEventRecord(ctx->lane_ev[l], ctx->lane_st[l - 1]));
+    if (sj == SIM_OK) sj = dev(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
+    if (sj != SIM_OK && s == SIM_OK) s = sj;
+  }
+  return s;
 }
 
 sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* t_fast,
@@ -1016,6 +1091,31 @@ sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
     if (value != SIM_ROW_PATH_AUTO && value != SIM_ROW_PATH_FUSED && value != SIM_ROW_PATH_SPLIT)
       return SIM_ERR_ARG;
     ctx->row_path = value;
+    return SIM_OK;
+  }
+  if (key == SIM_TUNE_UPDATE_LANES) {
+    if (value < 1 || value > kMaxUpdateLanes) return SIM_ERR_ARG;
+    if (value == ctx->lanes) return SIM_OK;
+    sim_status s = use_device(ctx);
+    if (s != SIM_OK) return s;
+    release_lanes(ctx);
+    bool ok = true;
+    for (int l = 1; l < value && ok; ++l) {
+      hipStream_t st = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+      if (ok) ctx->lane_st.push_back(st);
+    }
+    for (int i = 0; i < value && ok; ++i) {
+      hipEvent_t e = nullptr;
+      ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      if (ok) ctx->lane_ev.push_back(e);
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      release_lanes(ctx);
+      return SIM_ERR_DEVICE;
+    }
+    ctx->lanes = value;
     return SIM_OK;
   }
   return SIM_ERR_ARG;
@@ -1266,6 +1366,7 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
     lc.row_path = c->row_path;
     lc.capturing = c->capturing;
     lc.tab_slot = c->tab_slot;
+    lc.lanes = 1;
     lc.profiling = false;
     lc.used = 0;
     lc.dropped = 0;

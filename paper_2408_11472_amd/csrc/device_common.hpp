@@ -137,11 +137,12 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // Compile-time plan of an N = 2^LOG2N point transform held as E values per
-// thread (E in {8, 16}): an optional first stage of radix 2^(LOG2N mod log2 E),
-// then radix-E stages.
+// thread (E in {4, 8, 16}): an optional first stage of radix
+// 2^(LOG2N mod log2 E), then radix-E stages.
 template <int LOG2N, int E>
 struct FftPlan {
-  static constexpr int LE = (E == 16) ? 4 : 3;
+  static_assert(E == 4 || E == 8 || E == 16, "4, 8 or 16 values per thread");
+  static constexpr int LE = (E == 16) ? 4 : (E == 8) ? 3 : 2;
   static constexpr int REM = LOG2N % LE;
   static constexpr int NSTAGES = LOG2N / LE + (REM ? 1 : 0);
   static constexpr int radix(int s) { return (s == 0 && REM) ? (1 << REM) : E; }

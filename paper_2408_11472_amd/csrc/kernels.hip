@@ -19,7 +19,7 @@ namespace simk {
 
 // ---------------------------------------------------------------------------
 // Column pass.  Block = CPB adjacent columns x TPS threads per column; each
-// thread holds E = 16 spectral samples of its column at rows s + m * TPS.
+// thread holds E spectral samples of its column at rows s + m * TPS.
 //
 // With zeta(k, t) = 1/2 [c(k) e^{-i w t} + conj(c(-k)) e^{+i w t}] (Hermitian
 // in k) and its increment dzeta over dt, every real field F with multiplier
@@ -42,21 +42,25 @@ namespace simk {
 // pieces of rows and their mirrors.
 // Body of one column block: blk of nblk blocks (blockIdx.x and gridDim.x for
 // a plain launch, the work item and item count of a member in a batched one).
-template <typename Real, int LOG2NY, bool PREP>
+// OPAQUE_TID (the batched kernel): the thread index is made opaque per call,
+// so that nothing derived from it is hoisted out of the item loop and kept
+// live across it (which made that kernel spill).
+template <typename Real, int LOG2NY, bool PREP, int E, bool OPAQUE_TID>
 __device__ __forceinline__ void colpass_body(const cplx<Real>* __restrict__ spec,
                                              cplx<Real>* __restrict__ planes, const GridP& gp,
                                              double t, double dt,
                                              const cplx<Real>* __restrict__ tw, int blk,
                                              int nblk) {
-  constexpr int E = 16;
   constexpr int ny = 1 << LOG2NY;
   constexpr int TPS = ny / E;
   constexpr int CPB = col_cpb(LOG2NY, sizeof(cplx<Real>));
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<Real>* lds = reinterpret_cast<cplx<Real>*>(smem_raw);
   const int nx = gp.nx;
-  const int c = threadIdx.x % CPB;
-  const int s = threadIdx.x / CPB;
+  unsigned tid = threadIdx.x;
+  if constexpr (OPAQUE_TID) asm volatile("" : "+v"(tid));
+  const int c = tid % CPB;
+  const int s = tid / CPB;
   // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
   // contiguous run of (strip, group) items so that the two groups of a strip
   // and neighbouring strips, which share cache lines, meet in the same L2.
@@ -205,7 +209,8 @@ template <typename Real, int LOG2NY, bool PREP>
 __global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
 colpass_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restrict__ planes, GridP gp,
                double t, double dt, const cplx<Real>* __restrict__ tw) {
-  colpass_body<Real, LOG2NY, PREP>(spec, planes, gp, t, dt, tw, blockIdx.x, gridDim.x);
+  constexpr int E = col_e(LOG2NY, sizeof(cplx<Real>));
+  colpass_body<Real, LOG2NY, PREP, E, false>(spec, planes, gp, t, dt, tw, blockIdx.x, gridDim.x);
 }
 
 // The prepared spectrum of the column pass: for each column ix of the half
@@ -233,9 +238,8 @@ prepare_spectrum_kernel(const cplx<Real>* __restrict__ spec, cplx<Real>* __restr
 
 // ---------------------------------------------------------------------------
 // Row pass helpers.  Block = RPB rows x TPR threads per row; each thread holds
-// ER = 8 samples of its row at columns tr + m * TPR.
-
-constexpr int ER = kRowE;
+// ER samples of its row at columns tr + m * TPR (ER = 8, or 4 in the facet row
+// pass in double; a template parameter of every helper).
 
 // The six row transforms.  Transform q inverts A + i B along x (two real
 // fields in one complex transform), A and B taken from half planes a and b
@@ -287,7 +291,7 @@ __device__ __forceinline__ cplx<Real> pair_value(cplx<Real> a, cplx<Real> b, con
 
 // Half-plane column of slot m of thread tr (columns tr + m TPR of the row):
 // slots m < ER/2 hold columns below nx/2, the others mirror columns.
-template <int LOG2NX>
+template <int LOG2NX, int ER>
 __device__ __forceinline__ int half_col(int tr, int m) {
   constexpr int TPR = (1 << LOG2NX) / ER;
   return m < ER / 2 ? tr + m * TPR : (TPR - tr) + (ER - 1 - m) * TPR;
@@ -295,7 +299,7 @@ __device__ __forceinline__ int half_col(int tr, int m) {
 
 // Input of transform q for row iy, read from the half planes in the tiled
 // layout (tiles of 2^lw columns by 2^lh rows, rows 2^lhw wide).
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, int ER>
 __device__ __forceinline__ void load_pair_row(const cplx<Real>* __restrict__ planes, size_t psz,
                                               int q, int iy, bool valid, int tr, const GridP& gp,
                                               cplx<Real>* v) {
@@ -324,7 +328,7 @@ __device__ __forceinline__ void load_pair_row(const cplx<Real>* __restrict__ pla
   } else {
 #pragma unroll
     for (int m = 0; m < ER; ++m) {
-      const int col = half_col<LOG2NX>(tr, m);
+      const int col = half_col<LOG2NX, ER>(tr, m);
       const bool ok = valid && col < nx / 2;
       a[m] = ok ? pa[off(col)] : mk<Real>(0, 0);
       b[m] = (ok && ps.b >= 0) ? pb[off(col)] : mk<Real>(0, 0);
@@ -332,14 +336,14 @@ __device__ __forceinline__ void load_pair_row(const cplx<Real>* __restrict__ pla
   }
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
-    const int col = half_col<LOG2NX>(tr, m);
+    const int col = half_col<LOG2NX, ER>(tr, m);
     v[m] = pair_value(a[m], b[m], ps, dkx * (Real)col, m >= ER / 2, m == 0 && tr == 0);
   }
 }
 
 // A thread's own columns tr + m TPR (m < ER/2) of the two half planes of a
 // transform, loaded ahead of use.
-template <typename Real>
+template <typename Real, int ER>
 struct PairRegs {
   cplx<Real> a[ER / 2], b[ER / 2];
 };
@@ -349,10 +353,10 @@ struct PairRegs {
 // the two share is kept instead of read again (the row order of the
 // transforms, 3 1 0 2 4 5, puts the two users of half planes 2, 0 and 1
 // next to each other).
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, int ER>
 __device__ __forceinline__ void load_pair_direct(const cplx<Real>* __restrict__ planes,
                                                  size_t psz, int q, int iy, int tr,
-                                                 const GridP& gp, PairRegs<Real>& r,
+                                                 const GridP& gp, PairRegs<Real, ER>& r,
                                                  int q_cur = -1) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER, H = ER / 2;
   const PairSrc ps = pair_src(q);
@@ -393,8 +397,8 @@ __device__ __forceinline__ void load_pair_direct(const cplx<Real>* __restrict__ 
 // columns are read from there, so that every half-plane element is read
 // from memory once.  The barrier before the writes separates this
 // transform from the previous one's LDS use.
-template <typename Real, int LOG2NX>
-__device__ __forceinline__ void build_pair_x(const PairRegs<Real>& r, int q, int tr,
+template <typename Real, int LOG2NX, int ER>
+__device__ __forceinline__ void build_pair_x(const PairRegs<Real, ER>& r, int q, int tr,
                                              const GridP& gp, cplx<Real>* v, cplx<Real>* X) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER, H = ER / 2;
   const PairSrc ps = pair_src(q);
@@ -408,7 +412,7 @@ __device__ __forceinline__ void build_pair_x(const PairRegs<Real>& r, int q, int
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
-    const int col = half_col<LOG2NX>(tr, m);
+    const int col = half_col<LOG2NX, ER>(tr, m);
     cplx<Real> a, b;
     if (m < H) {
       a = r.a[m];
@@ -428,7 +432,7 @@ __device__ __forceinline__ void build_pair_x(const PairRegs<Real>& r, int q, int
 // a tile), or 4 bytes per lane for float planes in one-column tiles.
 // Completion is awaited with the vector-memory counter and a barrier before
 // S is read.
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, int ER>
 __device__ __forceinline__ void stage_half_row(const cplx<Real>* __restrict__ plane, int iy,
                                                const GridP& gp, cplx<Real>* S, int tr) {
   constexpr int nx = 1 << LOG2NX, TPR = nx / ER, W = TPR / 64, NH = nx / 2;
@@ -463,18 +467,19 @@ __device__ __forceinline__ void stage_half_row(const cplx<Real>* __restrict__ pl
 
 // Stages the inputs of transform q for row iy: half plane a into S[0, nx/2),
 // half plane b into S[nx/2, nx).
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, int ER>
 __device__ __forceinline__ void stage_pair(const cplx<Real>* __restrict__ planes, size_t psz,
                                            int q, int iy, const GridP& gp, cplx<Real>* S,
                                            int tr) {
   const PairSrc ps = pair_src(q);
-  stage_half_row<Real, LOG2NX>(planes + (size_t)ps.a * psz, iy, gp, S, tr);
+  stage_half_row<Real, LOG2NX, ER>(planes + (size_t)ps.a * psz, iy, gp, S, tr);
   if (ps.b >= 0)
-    stage_half_row<Real, LOG2NX>(planes + (size_t)ps.b * psz, iy, gp, S + (1 << LOG2NX) / 2, tr);
+    stage_half_row<Real, LOG2NX, ER>(planes + (size_t)ps.b * psz, iy, gp, S + (1 << LOG2NX) / 2,
+                                     tr);
 }
 
 // Input of transform q from its staged half rows.
-template <typename Real, int LOG2NX>
+template <typename Real, int LOG2NX, int ER>
 __device__ __forceinline__ void read_pair_lds(const cplx<Real>* S, int q, int tr, const GridP& gp,
                                               cplx<Real>* v) {
   constexpr int nx = 1 << LOG2NX;
@@ -482,7 +487,7 @@ __device__ __forceinline__ void read_pair_lds(const cplx<Real>* S, int q, int tr
   const Real dkx = (Real)(6.283185307179586476925 / ((double)nx * gp.dx));
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
-    const int col = half_col<LOG2NX>(tr, m);
+    const int col = half_col<LOG2NX, ER>(tr, m);
     const bool ok = m != ER / 2 || tr != 0;
     const cplx<Real> a = ok ? S[col] : mk<Real>(0, 0);
     const cplx<Real> b = (ok && ps.b >= 0) ? S[nx / 2 + col] : mk<Real>(0, 0);
@@ -501,38 +506,38 @@ struct NextRow {
 // recomputed per transform instead of being kept live across all six.
 // Staged mode: the input rows were loaded into S ahead of time; once every
 // thread has its values, the next transform's rows are put in flight into S.
-// Unstaged mode with lrow2 set: the exchanges alternate between lrow and
+// Unstaged mode with PP (lrow2 and pre set): the exchanges alternate between lrow and
 // lrow2 (one barrier each), the mirror columns of the input go through lrow2
 // before the first exchange writes lrow (build_pair_x), and the own columns
 // of the next transform are loaded into pre while this one runs.
-template <typename Real, int LOG2NX, bool STAGE>
+template <typename Real, int LOG2NX, int ER, bool STAGE, bool PP>
 __device__ __forceinline__ void row_transform(const cplx<Real>* __restrict__ planes, size_t psz,
                                               int q, int iy, bool valid, int tr,
                                               const GridP& gp, cplx<Real>* lrow, cplx<Real>* S,
                                               NextRow nxt, const cplx<Real>* __restrict__ tw,
                                               cplx<Real>* v, cplx<Real>* lrow2 = nullptr,
-                                              PairRegs<Real>* pre = nullptr) {
+                                              PairRegs<Real, ER>* pre = nullptr) {
   int trv = tr;
   asm volatile("" : "+v"(trv));
   if constexpr (STAGE) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    read_pair_lds<Real, LOG2NX>(S, q, trv, gp, v);
+    read_pair_lds<Real, LOG2NX, ER>(S, q, trv, gp, v);
     __syncthreads();
-    if (nxt.q >= 0) stage_pair<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, gp, S, trv);
+    if (nxt.q >= 0) stage_pair<Real, LOG2NX, ER>(planes, psz, nxt.q, nxt.iy, gp, S, trv);
     // after S: the LDS twiddles (nx/2) and the second exchange row; the two
     // barriers above separate this transform from the previous one
     constexpr int nx = 1 << LOG2NX;
     fft_seq<Real, LOG2NX, ER, 1, +1, true, true>(v, lrow, trv, S + nx, S + nx + nx / 2);
   } else {
-    if (lrow2) {
-      build_pair_x<Real, LOG2NX>(*pre, q, trv, gp, v, lrow2);
+    if constexpr (PP) {
+      build_pair_x<Real, LOG2NX, ER>(*pre, q, trv, gp, v, lrow2);
       if (nxt.q >= 0)
-        load_pair_direct<Real, LOG2NX>(planes, psz, nxt.q, nxt.iy, trv, gp, *pre,
-                                       nxt.iy == iy ? q : -1);
+        load_pair_direct<Real, LOG2NX, ER>(planes, psz, nxt.q, nxt.iy, trv, gp, *pre,
+                                           nxt.iy == iy ? q : -1);
       fft_seq<Real, LOG2NX, ER, 1, +1, false, true>(v, lrow, trv, tw, lrow2);
     } else {
-      load_pair_row<Real, LOG2NX>(planes, psz, q, iy, valid, trv, gp, v);
+      load_pair_row<Real, LOG2NX, ER>(planes, psz, q, iy, valid, trv, gp, v);
       fft_seq<Real, LOG2NX, ER, 1, +1>(v, lrow, trv, tw);
     }
   }
@@ -551,7 +556,7 @@ __device__ __forceinline__ void load_row_twiddles(cplx<Real>* dst,
 // 3 1 0 2 (geometry: the normal needs 3, 1 and 2; 0 gives the position), then
 // 4 5 (displacement over the pulse pair); each quantity is handed to emit(i,
 // values) as soon as it is formed, i its index in the facet SoA.
-template <typename Real>
+template <typename Real, int ER>
 struct RowFacets {
   Real Dx[ER], Dy[ER], h[ER], sx[ER], sy[ER], jac[ER], dDx[ER], dDy[ER], dh[ER];
 };
@@ -561,24 +566,24 @@ struct NoEmit {
   __device__ void operator()(int, const T*) const {}
 };
 
-template <typename Real, int LOG2NX, bool STAGE, typename Emit>
+template <typename Real, int LOG2NX, int ER, bool STAGE, bool PP, typename Emit>
 __device__ __forceinline__ void row_geometry(const cplx<Real>* __restrict__ planes, size_t psz,
                                              int iy, bool valid, int tr, const GridP& gp,
                                              cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                              const cplx<Real>* __restrict__ tw,
-                                             RowFacets<Real>& F, Emit emit,
+                                             RowFacets<Real, ER>& F, Emit emit,
                                              cplx<Real>* lrow2 = nullptr,
-                                             PairRegs<Real>* pre = nullptr) {
+                                             PairRegs<Real, ER>* pre = nullptr) {
   cplx<Real> v[ER];
   Real dxy[ER], dyy[ER], hx[ER];
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 3, iy, valid, tr, gp, lrow, S,
                                      NextRow{1, iy_stage}, tw, v, lrow2, pre);  // Dx_y + i Dy_y
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
     dxy[m] = v[m].x;
     dyy[m] = v[m].y;
   }
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 1, iy, valid, tr, gp, lrow, S,
                                      NextRow{0, iy_stage}, tw, v, lrow2, pre);  // Dy + i h_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
@@ -586,7 +591,7 @@ __device__ __forceinline__ void row_geometry(const cplx<Real>* __restrict__ plan
     hx[m] = v[m].y;
   }
   emit(1, F.Dy);
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 0, iy, valid, tr, gp, lrow, S,
                                      NextRow{2, iy_stage}, tw, v, lrow2, pre);  // h + i Dx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
@@ -595,7 +600,7 @@ __device__ __forceinline__ void row_geometry(const cplx<Real>* __restrict__ plan
   }
   emit(0, F.Dx);
   emit(2, F.h);
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 2, iy, valid, tr, gp, lrow, S,
                                      NextRow{4, iy_stage}, tw, v, lrow2, pre);  // h_y + i Dx_x
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
@@ -614,16 +619,16 @@ __device__ __forceinline__ void row_geometry(const cplx<Real>* __restrict__ plan
   emit(5, F.jac);
 }
 
-template <typename Real, int LOG2NX, bool STAGE, typename Emit>
+template <typename Real, int LOG2NX, int ER, bool STAGE, bool PP, typename Emit>
 __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes, size_t psz,
                                            int iy, bool valid, int tr, const GridP& gp,
                                            cplx<Real>* lrow, cplx<Real>* S, int iy_stage,
                                            int iy_next, const cplx<Real>* __restrict__ tw,
-                                           RowFacets<Real>& F, Emit emit,
+                                           RowFacets<Real, ER>& F, Emit emit,
                                            cplx<Real>* lrow2 = nullptr,
-                                           PairRegs<Real>* pre = nullptr) {
+                                           PairRegs<Real, ER>* pre = nullptr) {
   cplx<Real> v[ER];
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 4, iy, valid, tr, gp, lrow, S,
                                      NextRow{5, iy_stage}, tw, v, lrow2, pre);  // dh + i dDx
 #pragma unroll
   for (int m = 0; m < ER; ++m) {
@@ -633,7 +638,7 @@ __device__ __forceinline__ void row_motion(const cplx<Real>* __restrict__ planes
   emit(6, F.dDx);
   emit(8, F.dh);
   // the row after this one starts with transform 3 (iy_next < 0: none)
-  row_transform<Real, LOG2NX, STAGE>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
+  row_transform<Real, LOG2NX, ER, STAGE, PP>(planes, psz, 5, iy, valid, tr, gp, lrow, S,
                                      NextRow{iy_next >= 0 ? 3 : -1, iy_next}, tw, v, lrow2,
                                      pre);  // dDy
 #pragma unroll
@@ -648,8 +653,11 @@ __device__ __forceinline__ void rowpass_facets_body(const cplx<Real>* __restrict
                                                     int nblk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int nx = 1 << LOG2NX;
-  constexpr int TPR = row_tpr(LOG2NX);
-  constexpr int RPB = row_rpb(LOG2NX);
+  constexpr int cs = sizeof(cplx<Real>);
+  constexpr int ER = row_facets_er(LOG2NX, cs);
+  constexpr int TPR = row_facets_tpr(LOG2NX, cs);
+  constexpr int RPB = row_facets_rpb(LOG2NX, cs);
+  constexpr bool PP = row_facets_pp(LOG2NX, cs);
   const int ny = gp.ny;
   // No staging here: the wait for a staged row (vector-memory counter) would
   // also wait for this kernel's facet stores, which costs more than the load
@@ -659,9 +667,8 @@ __device__ __forceinline__ void rowpass_facets_body(const cplx<Real>* __restrict
   cplx<Real>* lrow = reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)rl * lpad(nx);
   cplx<Real>* S = nullptr;   // (no staging row)
   // second exchange buffer of this row (ping-pong exchanges), where it fits
-  cplx<Real>* lrow2 = row_facets_pp(LOG2NX, sizeof(cplx<Real>))
-                          ? reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)(RPB + rl) * lpad(nx)
-                          : nullptr;
+  cplx<Real>* lrow2 =
+      PP ? reinterpret_cast<cplx<Real>*>(smem_raw) + (size_t)(RPB + rl) * lpad(nx) : nullptr;
   const size_t psz = (size_t)ny << gp.lhw;
   // Workgroups are dealt to the 8 XCDs round robin: give each XCD a
   // contiguous run of row chunks, so that the chunks sharing a plane tile
@@ -670,9 +677,8 @@ __device__ __forceinline__ void rowpass_facets_body(const cplx<Real>* __restrict
 
   // with two exchange rows, the own columns of each transform's input are
   // loaded one transform ahead (first: transform 3 of the first row)
-  PairRegs<Real> pre;
-  if (row_facets_pp(LOG2NX, sizeof(cplx<Real>)))
-    load_pair_direct<Real, LOG2NX>(planes, psz, 3, q * RPB + rl, tr, gp, pre);
+  PairRegs<Real, ER> pre;
+  if (PP) load_pair_direct<Real, LOG2NX, ER>(planes, psz, 3, q * RPB + rl, tr, gp, pre);
   for (int iy0 = q * RPB; iy0 < ny; iy0 += nblk * RPB) {
     const int iy = iy0 + rl;
     const bool valid = iy < ny;
@@ -684,16 +690,16 @@ __device__ __forceinline__ void rowpass_facets_body(const cplx<Real>* __restrict
         for (int m = 0; m < ER; ++m) out.p[field][(size_t)iy * nx + tr + m * TPR] = val[m];
       }
     };
-    RowFacets<Real> F;
-    row_geometry<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw, F, emit,
-                                      lrow2, &pre);
-    row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next, tw,
-                                    F, emit, lrow2, &pre);
+    RowFacets<Real, ER> F;
+    row_geometry<Real, LOG2NX, ER, STAGE, PP>(planes, psz, iy, valid, tr, gp, lrow, S, iy, tw,
+                                              F, emit, lrow2, &pre);
+    row_motion<Real, LOG2NX, ER, STAGE, PP>(planes, psz, iy, valid, tr, gp, lrow, S, iy, iy_next,
+                                            tw, F, emit, lrow2, &pre);
   }
 }
 
 template <typename Real, int LOG2NX>
-__global__ void __launch_bounds__(row_threads(LOG2NX))
+__global__ void __launch_bounds__(row_facets_threads(LOG2NX, sizeof(cplx<Real>)))
 rowpass_facets_kernel(const cplx<Real>* __restrict__ planes, GridP gp, FacetPtrs<Real> out,
                       const cplx<Real>* __restrict__ tw) {
   rowpass_facets_body<Real, LOG2NX>(planes, gp, out, tw, blockIdx.x, gridDim.x);
@@ -721,6 +727,7 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
                           const cplx<Real>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int nx = 1 << LOG2NX;
+  constexpr int ER = kRowE;
   constexpr int TPR = row_tpr(LOG2NX);
   constexpr int RPB = row_rpb(LOG2NX);
   const int ny = gp.ny;
@@ -762,18 +769,19 @@ rowpass_accumulate_kernel(const cplx<Real>* __restrict__ planes, GridP gp, Radar
   // staged rows are clamped into the grid (a row past the band end is
   // transformed but not scattered)
   if (STAGE) load_row_twiddles<Real, LOG2NX>(S + nx, tw);   // ordered by the first barrier
-  if (STAGE && n_steps > 0) stage_pair<Real, LOG2NX>(planes, psz, 3, min(row_begin, ny - 1), gp, S, tr);
+  if (STAGE && n_steps > 0)
+    stage_pair<Real, LOG2NX, ER>(planes, psz, 3, min(row_begin, ny - 1), gp, S, tr);
   for (int k = 0; k < n_steps; ++k) {
     const int iy0 = row_begin + k * step_rows;
     const int iy = iy0 + rl;
     const bool valid = iy < row_end;
     const int iy_stage = min(iy, ny - 1);
     const int iy_next = k + 1 < n_steps ? min(iy0 + step_rows + rl, ny - 1) : -1;
-    RowFacets<Real> F;
-    row_geometry<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, tw, F,
-                                      NoEmit());
-    row_motion<Real, LOG2NX, STAGE>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage, iy_next,
-                                    tw, F, NoEmit());
+    RowFacets<Real, ER> F;
+    row_geometry<Real, LOG2NX, ER, STAGE, false>(planes, psz, iy, valid, tr, gp, lrow, S,
+                                                 iy_stage, tw, F, NoEmit());
+    row_motion<Real, LOG2NX, ER, STAGE, false>(planes, psz, iy, valid, tr, gp, lrow, S, iy_stage,
+                                               iy_next, tw, F, NoEmit());
     int key[ER];
     cplx<Real> cv[ER];
     // opaque row coordinates: the grid positions of the facets are
@@ -980,7 +988,8 @@ __device__ __forceinline__ void reduce_partials_body(const RadarP& rp, const Win
     if (threadIdx.x < 6) {
       unsigned long long sum = 0;
       for (int w2 = 0; w2 < nw; ++w2) sum += red[threadIdx.x][w2];
-      counters[threadIdx.x] += sum;
+      // atomic: updates of one run may overlap on several streams
+      atomicAdd(&counters[threadIdx.x], sum);
     }
   }
 }
@@ -1015,7 +1024,7 @@ __device__ __forceinline__ int next_item(int* queue, int* s_item) {
 }
 
 template <typename Real, int LOG2NY>
-__global__ void __launch_bounds__(col_threads(LOG2NY, sizeof(cplx<Real>)))
+__global__ void __launch_bounds__(col_threads_e(LOG2NY, sizeof(cplx<Real>), kColBatchE))
 colpass_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
                        int* __restrict__ queue, const cplx<Real>* __restrict__ tw) {
   __shared__ int s_item;
@@ -1024,13 +1033,14 @@ colpass_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items
     if (item >= n_items) break;
     const int m = item / per, blk = item - m * per;
     const BatchMember& b = mem[m];
-    colpass_body<Real, LOG2NY, true>((const cplx<Real>*)b.spec, (cplx<Real>*)b.planes, b.gp,
-                                     b.t, b.dt, tw, blk, per);
+    colpass_body<Real, LOG2NY, true, kColBatchE, true>((const cplx<Real>*)b.spec,
+                                                       (cplx<Real>*)b.planes, b.gp, b.t, b.dt,
+                                                       tw, blk, per);
   }
 }
 
 template <typename Real, int LOG2NX>
-__global__ void __launch_bounds__(row_threads(LOG2NX))
+__global__ void __launch_bounds__(row_facets_threads(LOG2NX, sizeof(cplx<Real>)))
 rowpass_facets_batched_kernel(const BatchMember* __restrict__ mem, int per, int n_items,
                               int* __restrict__ queue, const cplx<Real>* __restrict__ tw) {
   __shared__ int s_item;
@@ -1372,9 +1382,10 @@ hipError_t launch_prepare_spectrum(const void* spec, void* out, const GridP& gp,
 template <typename Real, int L>
 static hipError_t rowpass_facets_t(const void* planes, const GridP& gp, const FacetPtrs<Real>& fp,
                                    const void* tw, hipStream_t st) {
-  const int blocks = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
   constexpr int cs = sizeof(cplx<Real>);
-  hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks), dim3(row_threads(L)),
+  const int blocks = (gp.ny + row_facets_rpb(L, cs) - 1) / row_facets_rpb(L, cs);
+  hipLaunchKernelGGL((rowpass_facets_kernel<Real, L>), dim3(blocks),
+                     dim3(row_facets_threads(L, cs)),
                      row_facets_lds(L, cs), st,
                      (const cplx<Real>*)planes,
                      with_tiles<Real>(gp), fp, (const cplx<Real>*)tw);
@@ -1471,8 +1482,9 @@ static hipError_t colpass_batched_t(const BatchMember* mem, int n_mem, const Gri
     const int per = 2 * strips;
     const int n = n_mem * per;
     const void* k = (const void*)colpass_batched_kernel<Real, L>;
-    const int grid = persistent_grid(k, col_threads(L, cs), col_lds(L, cs), n);
-    hipLaunchKernelGGL((colpass_batched_kernel<Real, L>), dim3(grid), dim3(col_threads(L, cs)),
+    const int grid = persistent_grid(k, col_threads_e(L, cs, kColBatchE), col_lds(L, cs), n);
+    hipLaunchKernelGGL((colpass_batched_kernel<Real, L>), dim3(grid),
+                       dim3(col_threads_e(L, cs, kColBatchE)),
                        col_lds(L, cs), st, mem, per, n, queue, (const cplx<Real>*)tw);
     return hipGetLastError();
   }
@@ -1482,11 +1494,12 @@ template <typename Real, int L>
 static hipError_t rowpass_batched_t(const BatchMember* mem, int n_mem, const GridP& gp,
                                     int* queue, const void* tw, hipStream_t st) {
   constexpr int cs = sizeof(cplx<Real>);
-  const int per = (gp.ny + row_rpb(L) - 1) / row_rpb(L);
+  const int per = (gp.ny + row_facets_rpb(L, cs) - 1) / row_facets_rpb(L, cs);
   const int n = n_mem * per;
   const void* k = (const void*)rowpass_facets_batched_kernel<Real, L>;
-  const int grid = persistent_grid(k, row_threads(L), row_facets_lds(L, cs), n);
-  hipLaunchKernelGGL((rowpass_facets_batched_kernel<Real, L>), dim3(grid), dim3(row_threads(L)),
+  const int grid = persistent_grid(k, row_facets_threads(L, cs), row_facets_lds(L, cs), n);
+  hipLaunchKernelGGL((rowpass_facets_batched_kernel<Real, L>), dim3(grid),
+                     dim3(row_facets_threads(L, cs)),
                      row_facets_lds(L, cs), st, mem, per, n, queue, (const cplx<Real>*)tw);
   return hipGetLastError();
 }

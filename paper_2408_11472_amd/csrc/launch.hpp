@@ -22,9 +22,22 @@ constexpr int kMaxLog2Row = 13;             // .. 8192 along x
 
 __host__ __device__ constexpr size_t lpad_c(size_t i) { return i + (i >> 4); }
 
-// Column pass: CPB adjacent columns per block, ny/16 threads per column,
-// as many columns as fit kColLds of LDS (one column at least).
+// Column pass: CPB adjacent columns per block, ny/E threads per column, as
+// many columns as fit kColLds of LDS (one column at least).  E values per
+// thread: 16, or 8 in double on columns of 4096 and more (measured on the
+// 4096^2 track: 29.5 -> 26.7 ms of column pass per step; half the registers
+// per thread, so a CU holds twice the waves).  At those sizes the LDS alone
+// sets CPB, so the plane tiles are the same for 8 and 16 values, and the
+// persistent batched column pass keeps 16 (kColBatchE: its 1024-thread
+// blocks of 8 values would spill).
 constexpr size_t kColLds = kLdsBudget;
+#ifndef SIMK_COL_E64
+#define SIMK_COL_E64 8
+#endif
+constexpr int kColBatchE = 16;
+__host__ __device__ constexpr int col_e(int log2ny, int cs) {
+  return (cs == 16 && log2ny >= 12) ? SIMK_COL_E64 : 16;
+}
 // Short columns (ny <= kColSmallNy) get blocks of at most kColSmallThreads
 // threads, so that grids of 1024^2 and 2048^2 still launch hundreds of blocks
 // (measured: the 1024^2 regular-mode run 532 -> 461 ms, the 2048^2 gradient
@@ -37,13 +50,16 @@ constexpr int kColSmallNy = 2048;
 __host__ __device__ constexpr int col_cpb(int log2ny, int cs) {
   const int cap = (1 << log2ny) <= kColSmallNy ? kColSmallThreads : 1024;
   int cpb = 16;
-  while (cpb > 1 && ((long)cpb * ((1 << log2ny) / 16) > cap ||
+  while (cpb > 1 && ((long)cpb * ((1 << log2ny) / col_e(log2ny, cs)) > cap ||
                      (size_t)cpb * lpad_c((size_t)1 << log2ny) * cs > kColLds))
     cpb >>= 1;
   return cpb;
 }
+__host__ __device__ constexpr int col_threads_e(int log2ny, int cs, int e) {
+  return col_cpb(log2ny, cs) * ((1 << log2ny) / e);
+}
 __host__ __device__ constexpr int col_threads(int log2ny, int cs) {
-  return col_cpb(log2ny, cs) * ((1 << log2ny) / 16);
+  return col_threads_e(log2ny, cs, col_e(log2ny, cs));
 }
 __host__ __device__ constexpr size_t col_lds(int log2ny, int cs) {
   return (size_t)col_cpb(log2ny, cs) * lpad_c((size_t)1 << log2ny) * cs;
@@ -94,6 +110,28 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
   return (size_t)row_rpb(log2nx) * lpad_c((size_t)1 << log2nx) * cs;
 }
 
+// Values per thread of the facet row pass (split row path): 8, or
+// SIMK_ROW_E64 in double (4: 1024-thread blocks of radix-4 stages, with half
+// the registers per thread of 8 values, so that a CU holds twice the waves).
+#ifndef SIMK_ROW_E64
+#define SIMK_ROW_E64 8
+#endif
+__host__ __device__ constexpr int row_facets_er(int log2nx, int cs) {
+  return (cs == 16 && (1 << log2nx) / SIMK_ROW_E64 <= 1024) ? SIMK_ROW_E64 : kRowE;
+}
+__host__ __device__ constexpr int row_facets_tpr(int log2nx, int cs) {
+  return (1 << log2nx) / row_facets_er(log2nx, cs);
+}
+__host__ __device__ constexpr int row_facets_rpb(int log2nx, int cs) {
+  return row_facets_tpr(log2nx, cs) >= 256 ? 1 : 256 / row_facets_tpr(log2nx, cs);
+}
+__host__ __device__ constexpr int row_facets_threads(int log2nx, int cs) {
+  return row_facets_rpb(log2nx, cs) * row_facets_tpr(log2nx, cs);
+}
+__host__ __device__ constexpr size_t row_facets_fft_lds(int log2nx, int cs) {
+  return (size_t)row_facets_rpb(log2nx, cs) * lpad_c((size_t)1 << log2nx) * cs;
+}
+
 // Staging of the next transform's input in LDS for the fused row pass
 // (direct global -> LDS loads of the two half-plane rows it is built from
 // while the current row transform runs), for single-row blocks whose LDS
@@ -107,10 +145,10 @@ constexpr size_t kFusedFrontMax = 120 * 1024;
 // The facet row pass alternates its exchanges between two transform rows
 // where both fit the LDS budget.
 __host__ __device__ constexpr bool row_facets_pp(int log2nx, int cs) {
-  return 2 * row_fft_lds(log2nx, cs) <= kLdsBudget;
+  return 2 * row_facets_fft_lds(log2nx, cs) <= kLdsBudget;
 }
 __host__ __device__ constexpr size_t row_facets_lds(int log2nx, int cs) {
-  return (row_facets_pp(log2nx, cs) ? 2 : 1) * row_fft_lds(log2nx, cs);
+  return (row_facets_pp(log2nx, cs) ? 2 : 1) * row_facets_fft_lds(log2nx, cs);
 }
 __host__ __device__ constexpr size_t row_stage_bytes(bool stage, int log2nx, int cs) {
   return stage ? ((size_t)cs << log2nx) + ((size_t)cs << (log2nx - 1)) +

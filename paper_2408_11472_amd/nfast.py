@@ -188,10 +188,12 @@ def compare_waveforms(Y_fast, Y_reg, gate_floor=0.01):
     }
 
 
-def sweep(scene, n_fasts, precision, torch, with_iq=False, max_lag=32):
+def sweep(scene, n_fasts, precision, torch, with_iq=False, max_lag=32, tune=False):
     """Run the regular mode and every n_fast on the scene; returns a dict per
     mode: time, speed-up over the regular mode, facet-updates/s and (fast
-    modes) the fidelity against the regular mode over the mode's pulses."""
+    modes) the fidelity against the regular mode over the mode's pulses.
+    tune: each mode's launch parameters (row path, update lanes) from the
+    autotuner first (its choice is recorded as "tuning")."""
     from . import inputs, simradar
     g = scene.grid
     spec = inputs.sea_spectrum(g.nx, g.ny, g.dx, g.dy, scene.sea.swh, scene.sea.peak_wavelength,
@@ -205,6 +207,13 @@ def sweep(scene, n_fasts, precision, torch, with_iq=False, max_lag=32):
     for nf in (1,) + tuple(n_fasts):
         wl = mode(scene, nf)
         sim = simradar.Simulator(g, wl.radar, precision)
+        tuning = None
+        if tune:
+            from . import autotune
+            e = autotune.tune(sim, spec_t, use_cache=False,
+                              run_times=[wl.update_time(j) for j in range(wl.n_spec)])
+            tuning = {"row_path": e["row_path"], "row_bands": e["row_bands"],
+                      "update_lanes": e["update_lanes"]}
         prep = sim.prepare_spectrum(spec_t)
         run_mode(sim, prep, wl, torch)                 # warm-up (code objects, caches)
         t0 = time.perf_counter()
@@ -215,6 +224,8 @@ def sweep(scene, n_fasts, precision, torch, with_iq=False, max_lag=32):
                "pulses": wl.n_pulses, "gpu_s": dt, "wall_s": wall,
                "facet_updates_per_s": wl.n_facets * wl.n_spec / dt,
                "iq_pulses_per_s": wl.n_pulses / dt}
+        if tuning is not None:
+            rec["tuning"] = tuning
         if nf == 1:
             Y_reg, t_reg = Yh, dt
         else:

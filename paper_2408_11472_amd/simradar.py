@@ -48,7 +48,7 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_get_precision", "sim_workspace_size", "sim_set_workspace",
             "sim_surface_update", "sim_range_doppler_accumulate",
             "sim_range_doppler_accumulate_noalloc", "sim_update_and_accumulate", "sim_prepared_spectrum_size", "sim_prepare_spectrum",
-            "sim_update_and_accumulate_prepared", "sim_segments_to_iq",
+            "sim_update_and_accumulate_prepared", "sim_run_updates", "sim_segments_to_iq",
             "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
             "sim_range_doppler_accumulate_adjoint",
             "sim_batch_create", "sim_batch_destroy", "sim_batch_workspace_size",
@@ -59,6 +59,7 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
 
 SIM_TUNE_ROW_BANDS = 0
 SIM_TUNE_ROW_PATH = 1
+SIM_TUNE_UPDATE_LANES = 2
 SIM_ROW_PATH_AUTO, SIM_ROW_PATH_FUSED, SIM_ROW_PATH_SPLIT = 0, 1, 2
 
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
@@ -143,6 +144,8 @@ _sig = {
     "sim_update_and_accumulate_prepared": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P,
                                                           ctypes.POINTER(sim_radar), _D, _I, _P,
                                                           _I, _P, _P, _P]),
+    "sim_run_updates": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid), _P, ctypes.POINTER(sim_radar),
+                                       _I, _I, ctypes.POINTER(ctypes.c_double), _P, _I, _P, _P]),
     "sim_segments_to_iq": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P]),
     "sim_waveform_loss": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P, _P, _P]),
     "sim_waveform_loss_adjoint": (ctypes.c_int, [_P, ctypes.POINTER(sim_radar), _P, _I, _P, _P,
@@ -274,6 +277,15 @@ def sim_update_and_accumulate_prepared(ctx, grid, prepared_ptr, radar, t, j, t_f
            _lib.sim_update_and_accumulate_prepared(ctx, ctypes.byref(grid), prepared_ptr,
                                                    ctypes.byref(radar), t, j, t_fast_ptr, n_spec,
                                                    counters_ptr, code_ptr, stream))
+
+
+def sim_run_updates(ctx, grid, prepared_ptr, radar, j0, times, t_fast_ptr, n_spec, counters_ptr,
+                    stream) -> None:
+    """times: sequence of the pulse times of updates j0, j0 + 1, ..."""
+    arr = (ctypes.c_double * len(times))(*[float(x) for x in times])
+    _check("sim_run_updates",
+           _lib.sim_run_updates(ctx, ctypes.byref(grid), prepared_ptr, ctypes.byref(radar), j0,
+                                len(times), arr, t_fast_ptr, n_spec, counters_ptr, stream))
 
 
 def sim_segments_to_iq(ctx, radar, t_fast_ptr, n_spec, y_ptr, stream) -> None:
@@ -439,8 +451,15 @@ class Simulator:
         self.grid = grid_struct(grid)
         self.radar = radar_struct(radar)
         self.ctx = sim_create(device, precision)
+        self.lanes = 1
+        self._alloc_workspace()
+
+    def _alloc_workspace(self):
+        """Workspace of the context's current lane count (sim_workspace_size)."""
         nbytes = sim_workspace_size(self.ctx, self.grid, self.radar)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.workspace = None
+        self.workspace = self.torch.empty(nbytes + 256, dtype=self.torch.uint8,
+                                          device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) & ~255
         sim_set_workspace(self.ctx, self._ws_ptr, nbytes)
@@ -595,6 +614,18 @@ class Simulator:
     def set_row_path(self, path: int):
         """Row path of update_and_accumulate: SIM_ROW_PATH_AUTO, _FUSED or _SPLIT."""
         sim_set_tuning(self.ctx, SIM_TUNE_ROW_PATH, int(path))
+
+    def set_update_lanes(self, lanes: int):
+        """Streams run_updates deals the updates to (1 .. 4); the workspace is
+        re-made for that many lanes (work queued on the old one must be done:
+        the device is synchronised first)."""
+        lanes = int(lanes)
+        if lanes == self.lanes:
+            return
+        self.torch.cuda.synchronize(self.device)
+        sim_set_tuning(self.ctx, SIM_TUNE_UPDATE_LANES, lanes)
+        self.lanes = lanes
+        self._alloc_workspace()
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop per-kernel event timing."""
@@ -759,11 +790,24 @@ class Simulator:
         t_fast = t_fast if t_fast is not None else self.empty_spectra(n_updates + 1)
         r = self.radar
         prep = prepared if prepared is not None else self.prepare_spectrum(spec0, stream=stream)
-        for j in range(n_updates + 1):
-            t = (j * r.n_fast) / r.prf_hz
-            self.update_and_accumulate_prepared(prep, t, j, t_fast, counters=counters,
-                                                stream=stream)
+        self.run_updates(prep, [(j * r.n_fast) / r.prf_hz for j in range(n_updates + 1)], 0,
+                         t_fast, counters=counters, stream=stream)
         return t_fast, self.segments_to_iq(t_fast, y, stream=stream)
+
+    def run_updates(self, prepared, times, j0, t_fast, counters=None, stream=None):
+        """Updates j0 .. j0 + len(times) - 1 (update j0 + i at times[i]) in
+        one library call."""
+        r = self.radar
+        n_spec = t_fast.shape[0]
+        sim_run_updates(
+            self.ctx, self.grid,
+            self._need(prepared, self.complex_dtype, (self._prepared_elems(),), "prepared"),
+            self.radar, int(j0), times,
+            self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
+            n_spec,
+            None if counters is None else self._need(counters, self.torch.int64, (6,), "counters"),
+            self._stream(stream))
+        return t_fast
 
 
 def check_batch_buffers(grids, radars, updates, specs, T, Y, complex_dtype):

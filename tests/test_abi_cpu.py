@@ -57,6 +57,9 @@ def test_host_side_argument_checks():
     assert lib.sim_update_and_accumulate(None, ctypes.byref(g), None, ctypes.byref(r), 0.0, 0, None,
                                          1, None, None, None) == s.SIM_ERR_ARG
     assert lib.sim_segments_to_iq(None, ctypes.byref(r), None, 2, None, None) == s.SIM_ERR_ARG
+    times = (ctypes.c_double * 2)(0.0, 1e-3)
+    assert lib.sim_run_updates(None, ctypes.byref(g), None, ctypes.byref(r), 0, 2, times, None,
+                               2, None, None) == s.SIM_ERR_ARG
     assert lib.sim_destroy(None) == s.SIM_OK
     assert lib.sim_set_workspace(None, None, 0) == s.SIM_ERR_ARG
 

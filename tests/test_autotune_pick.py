@@ -22,3 +22,22 @@ def test_tie_within_margin_goes_to_split():
 
 def test_without_split_candidate():
     assert at.pick({(F, 128): 2.0, (F, 256): 1.0}) == (F, 256)
+
+
+def test_lanes_fastest_unless_fewer_within_margin():
+    assert at.pick_lanes({1: 458.0, 2: 283.0, 3: 224.0, 4: 226.0}) == 3
+    # the tuner's times on the 4096^2 track and the 8192 x 16384 stress runs
+    assert at.pick_lanes({1: 19.163, 2: 18.646, 3: 17.726, 4: 17.671}) == 3
+    assert at.pick_lanes({1: 194.263, 2: 194.622, 3: 188.512, 4: 193.235}) == 1
+    # 3 and 4 lanes within the margin of each other: the fewer kept
+    assert at.pick_lanes({1: 100.0, 2: 80.0, 3: 70.5, 4: 70.0}) == 3
+    # no lane count beats one by more than the margin
+    assert at.pick_lanes({1: 100.0, 2: 99.0, 3: 97.0, 4: 99.5}) == 1
+
+
+def test_sample_times_spread_over_the_run():
+    t = [0.1 * j for j in range(513)]
+    s = at.sample_times(t, 24)
+    assert len(s) == 24 and s[0] == t[0] and s[-1] == t[-1]
+    assert all(b > a for a, b in zip(s, s[1:]))
+    assert at.sample_times(t[:10], 24) == t[:10]

@@ -119,12 +119,25 @@ def test_band_count_changes_only_summation_order(prec, pcode, cdt, tol, tmp_path
         outs.append(T.cpu().numpy())
     for o in outs[1:]:
         assert rel_l2(o, outs[0]) <= tol
-    entry = autotune.tune(sim, spec, repeats=2)
+    entry = autotune.tune(sim, spec, repeats=2,
+                          run_times=[wl.update_time(j) for j in range(wl.n_spec)])
     assert entry["row_path"] in (autotune.PATH_FUSED, autotune.PATH_SPLIT)
     if entry["row_path"] == autotune.PATH_FUSED:
         assert entry["row_bands"] in autotune.CANDIDATE_BANDS
+    assert entry["update_lanes"] in autotune.CANDIDATE_LANES
+    assert sim.lanes == entry["update_lanes"]
     again = autotune.tune(sim, spec)                                       # cached
-    assert (again["row_path"], again["row_bands"]) == (entry["row_path"], entry["row_bands"])
+    assert (again["row_path"], again["row_bands"], again["update_lanes"]) == \
+        (entry["row_path"], entry["row_bands"], entry["update_lanes"])
+    # the tuned context still computes the same spectrum
+    T = sim.empty_spectra(wl.n_spec)
+    sim.run(None, wl.n_updates, t_fast=T, prepared=sim.prepare_spectrum(spec))
+    torch.cuda.synchronize()
+    T_one = sim.empty_spectra(wl.n_spec)
+    for j in range(wl.n_spec):
+        sim.update_and_accumulate(spec, wl.update_time(j), j, T_one)
+    torch.cuda.synchronize()
+    assert rel_l2(T.cpu().numpy(), T_one.cpu().numpy()) <= tol
     sim.close()
 
 
