@@ -49,10 +49,10 @@ LAYOUT_SHARE = {"surface_colpass": 8 + 32, "surface_rowpass": 32, "fused_rowpass
 # they were taken on.
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "db00451ed9060564",
-    "fp32": {"surface_colpass": 828e6, "surface_rowpass": 1141e6,
+    "source_sha": "75579d9f68437a3e",
+    "fp32": {"surface_colpass": 817e6, "surface_rowpass": 1141e6,
              "accumulate_facets": 607e6, "reduce_partials": 3e6},
-    "fp64": {"surface_colpass": 1345e6, "surface_rowpass": 2283e6,
+    "fp64": {"surface_colpass": 1347e6, "surface_rowpass": 2283e6,
              "accumulate_facets": 1211e6, "reduce_partials": 3e6},
 }
 PER_UPDATE_KERNELS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
