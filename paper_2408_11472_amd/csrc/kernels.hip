@@ -1069,10 +1069,9 @@ accumulate_facets_batched_kernel(const BatchMember* __restrict__ mem, int per, i
     FacetPtrs<Real> fp;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fp.p[i] = (Real*)b.fac[i];
-    GridP gp = b.gp;
-    RadarP rp = b.rp;
-    pin_scatter_constants(gp, rp);
-    accumulate_facets_body<Real>(fp, gp, rp, b.wp, (cplx<Real>*)b.Tj, nullptr, blk);
+    // (the constants stay scalar here: in vector registers they take this
+    // kernel past 128 VGPRs and halve the blocks a CU holds)
+    accumulate_facets_body<Real>(fp, b.gp, b.rp, b.wp, (cplx<Real>*)b.Tj, nullptr, blk);
   }
 }
 

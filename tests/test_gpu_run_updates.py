@@ -77,6 +77,14 @@ def test_run_updates_rejects_bad_arguments_before_launch():
     assert not T.cpu().numpy().any()                            # nothing launched
     assert call(1, [1e-3, 2e-3]) == s.SIM_OK
     torch.cuda.synchronize()
+    # more lanes without a workspace re-sized for them: refused before launch
+    T.zero_()
+    assert lib.sim_set_tuning(sim.ctx, s.SIM_TUNE_UPDATE_LANES, 3) == s.SIM_OK
+    assert lib.sim_set_tuning(sim.ctx, s.SIM_TUNE_UPDATE_LANES, 5) == s.SIM_ERR_ARG
+    assert lib.sim_set_tuning(sim.ctx, s.SIM_TUNE_UPDATE_LANES, 0) == s.SIM_ERR_ARG
+    assert call(0, [0.0, 1e-3, 2e-3]) == s.SIM_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    assert not T.cpu().numpy().any()
     sim.close()
 
 
