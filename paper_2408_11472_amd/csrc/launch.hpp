@@ -111,8 +111,10 @@ __host__ __device__ constexpr size_t row_fft_lds(int log2nx, int cs) {
 }
 
 // Values per thread of the facet row pass (split row path): 8, or
-// SIMK_ROW_E64 in double (4: 1024-thread blocks of radix-4 stages, with half
-// the registers per thread of 8 values, so that a CU holds twice the waves).
+// SIMK_ROW_E64 in double.  4 gives 1024-thread blocks of radix-4 stages with
+// half the registers per thread, so a CU holds twice the waves; measured on
+// the 4096^2 track it was slower (56.2 against 51.5 ms of row pass per FP64
+// step: the two extra LDS exchanges per transform cost more), so 8 stays.
 #ifndef SIMK_ROW_E64
 #define SIMK_ROW_E64 8
 #endif
