@@ -571,6 +571,22 @@ def main_gradient(a, wl):
         gh, gsx, gsy = torch.autograd.grad(L, (h, sx, sy))
         return L, gh
 
+    # update lanes of the run calls (forward accumulate, adjoint): a few
+    # whole steps on each lane count, the fewest within 1 % of the fastest
+    lanes_ms = {}
+    if not a.no_autotune:
+        from paper_2408_11472_amd import autotune
+        for lanes in autotune.CANDIDATE_LANES:
+            sim.set_update_lanes(lanes)
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                step()
+            torch.cuda.synchronize()
+            lanes_ms[lanes] = (time.perf_counter() - t0) / 5 * 1e3
+        sim.set_update_lanes(autotune.pick_lanes(lanes_ms, margin=0.01))
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -589,6 +605,8 @@ def main_gradient(a, wl):
                    "step": "forward + backward of the waveform loss", "range_phase": "f64",
                    "parallelism": "single-gpu"},
         "loss": float(L.detach()), "grad_h_finite": bool(torch.isfinite(gh).all().item()),
+        "update_lanes": sim.lanes,
+        "lanes_ms_per_step": {str(k): round(v, 3) for k, v in lanes_ms.items()} or None,
     }
     print(json.dumps(line), flush=True)
     sim.close()

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 5
+#define SIM_ABI_VERSION 6
 
 typedef enum sim_status {
   SIM_OK = 0,
@@ -264,7 +264,8 @@ sim_status sim_update_and_accumulate_prepared(sim_ctx *ctx, const sim_grid *grid
  *             0 <= j0 and j0 + count <= n_spec.
  *   counters  device sim_counters, accumulated over the updates; may be NULL.
  * Arguments are checked before anything is launched (every time must be
- * finite); a launch error stops the loop and is returned. */
+ * finite; with L lanes the workspace must hold L one-lane workspaces, else
+ * SIM_ERR_WORKSPACE); a launch error stops the loop and is returned. */
 sim_status sim_run_updates(sim_ctx *ctx, const sim_grid *grid, const void *prepared,
                            const sim_radar *radar, int32_t j0, int32_t count,
                            const double *times, void *t_fast, int32_t n_spec,
@@ -320,6 +321,28 @@ sim_status sim_range_doppler_accumulate_adjoint(sim_ctx *ctx, const sim_grid *gr
                                                 const void *t_fast_bar, int32_t n_spec,
                                                 void *grad_h, void *grad_sx, void *grad_sy,
                                                 void *stream);
+
+/* sim_range_doppler_accumulate and its adjoint for the updates j0 .. j0 +
+ * count - 1 of a run in one call, on stacked facet sets: field f of update
+ * j0 + i is at facets->f + i ny nx elements (each field a [count][ny][nx]
+ * array), update j0 + i at time times[i] (host array of count times, read
+ * during the call); grad_h, grad_sx, grad_sy likewise [count][ny][nx].  The
+ * updates are dealt to the update lanes as in sim_run_updates (the forward
+ * one needs a workspace slice per lane, the adjoint none); results are those
+ * of the per-update calls (the adjoint's bit for bit: a per-facet gather).
+ * Arguments are checked before anything is launched. */
+sim_status sim_range_doppler_accumulate_run(sim_ctx *ctx, const sim_grid *grid,
+                                            const sim_facets *facets, const sim_radar *radar,
+                                            int32_t j0, int32_t count, const double *times,
+                                            void *t_fast, int32_t n_spec,
+                                            sim_counters *counters, void *stream);
+sim_status sim_range_doppler_accumulate_adjoint_run(sim_ctx *ctx, const sim_grid *grid,
+                                                    const sim_facets *facets,
+                                                    const sim_radar *radar, int32_t j0,
+                                                    int32_t count, const double *times,
+                                                    const void *t_fast_bar, int32_t n_spec,
+                                                    void *grad_h, void *grad_sx, void *grad_sy,
+                                                    void *stream);
 
 /* ---- look-up tables of the facet amplitude ---------------------------------
  * Sec. II.A: the antenna patterns of a simulation are recorded on a u-v grid

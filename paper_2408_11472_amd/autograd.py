@@ -16,9 +16,10 @@ from . import simradar
 FIXED_FIELDS = ("disp_x", "disp_y", "jac", "ddisp_x", "ddisp_y", "dh")
 
 
-def _facets(fixed, h, sx, sy, j):
-    f = {k: fixed[k][j] for k in FIXED_FIELDS}
-    f["h"], f["sx"], f["sy"] = h[j], sx[j], sy[j]
+def _stacked(fixed, h, sx, sy):
+    """The run's facet sets, every field [n_spec][ny][nx]."""
+    f = dict(fixed)
+    f["h"], f["sx"], f["sy"] = h, sx, sy
     return f
 
 
@@ -32,8 +33,7 @@ class WaveformLoss(torch.autograd.Function):
     def forward(ctx, h, sx, sy, sim, fixed, times, target):
         n_spec = h.shape[0]
         T = sim.empty_spectra(n_spec)
-        for j in range(n_spec):
-            sim.range_doppler_accumulate(_facets(fixed, h, sx, sy, j), times[j], j, T)
+        sim.range_doppler_accumulate_run(_stacked(fixed, h, sx, sy), times[:n_spec], 0, T)
         Y = sim.segments_to_iq(T)
         P, L = sim.waveform_loss(Y, target)
         ctx.save_for_backward(h, sx, sy, Y, P, target)
@@ -51,9 +51,8 @@ class WaveformLoss(torch.autograd.Function):
         gh = torch.empty_like(h)
         gsx = torch.empty_like(sx)
         gsy = torch.empty_like(sy)
-        for j in range(n_spec):
-            sim.range_doppler_accumulate_adjoint(_facets(ctx.fixed, h, sx, sy, j), ctx.times[j],
-                                                 j, Tb, out=(gh[j], gsx[j], gsy[j]))
+        sim.range_doppler_accumulate_adjoint_run(_stacked(ctx.fixed, h, sx, sy),
+                                                 ctx.times[:n_spec], 0, Tb, (gh, gsx, gsy))
         return gh, gsx, gsy, None, None, None, None
 
 

@@ -82,12 +82,13 @@ def pick(times: dict) -> tuple:
     return best
 
 
-def pick_lanes(times: dict) -> int:
+def pick_lanes(times: dict, margin: float = LANES_MARGIN) -> int:
     """The lane count to use from the run time of each candidate: the
-    fastest, unless fewer lanes are within LANES_MARGIN of it."""
+    fastest, unless fewer lanes are within `margin` of it (LANES_MARGIN for
+    the tuner's short runs; a caller timing whole steps can use less)."""
     best = min(times, key=times.get)
     for n in sorted(times):
-        if n < best and times[n] <= times[best] * (1 + LANES_MARGIN):
+        if n < best and times[n] <= times[best] * (1 + margin):
             return n
     return best
 

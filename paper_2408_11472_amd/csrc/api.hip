@@ -362,6 +362,69 @@ void release_lanes(sim_ctx* c) {
   c->lanes = 1;
 }
 
+// Runs body(i, stream) for i in [0, count): on the caller's stream `st` when
+// the context has one lane, else dealt round robin to its lanes (lane 0 is
+// `st`; the lanes are forked from `st` by an event and joined back to it, so
+// the whole is ordered on `st`, also under graph capture).  With ws_slice >
+// 0 each lane enqueues with its own workspace slice (l * ws_slice; the
+// workspace must hold one per lane).  Stops at the first error; always joins.
+template <typename Body>
+sim_status run_on_lanes(sim_ctx* ctx, int32_t count, size_t ws_slice, hipStream_t st, Body body) {
+  const int NL = count > 1 ? std::min(ctx->lanes, (int)count) : 1;
+  sim_status s = SIM_OK;
+  if (NL == 1) {
+    for (int32_t i = 0; i < count && s == SIM_OK; ++i) s = body(i, st);
+    return s;
+  }
+  if (ws_slice && ctx->ws_bytes < (size_t)ctx->lanes * ws_slice) return SIM_ERR_WORKSPACE;
+  s = use_device(ctx);
+  if (s != SIM_OK) return s;
+  s = dev(hipEventRecord(ctx->lane_ev[0], st));
+  for (int l = 1; l < NL && s == SIM_OK; ++l)
+    s = dev(hipStreamWaitEvent(ctx->lane_st[l - 1], ctx->lane_ev[0], 0));
+  if (s != SIM_OK) return s;
+  void* const ws0 = ctx->ws;
+  const size_t ws_bytes0 = ctx->ws_bytes;
+  if (ws_slice) ctx->ws_bytes = ws_slice;
+  for (int32_t i = 0; i < count && s == SIM_OK; ++i) {
+    const int l = i % NL;
+    if (ws_slice) ctx->ws = (char*)ws0 + (size_t)l * ws_slice;
+    s = body(i, l ? ctx->lane_st[l - 1] : st);
+  }
+  ctx->ws = ws0;
+  ctx->ws_bytes = ws_bytes0;
+  for (int l = 1; l < NL; ++l) {
+    sim_status sj = dev(hipEventRecord(ctx->lane_ev[l], ctx->lane_st[l - 1]));
+    if (sj == SIM_OK) sj = dev(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
+    if (sj != SIM_OK && s == SIM_OK) s = sj;
+  }
+  return s;
+}
+
+// The facet set of update i of a stacked run (every field advanced by i
+// fields of `field_bytes`).
+sim_facets stacked_facets(const sim_facets& f, int32_t i, size_t field_bytes) {
+  const size_t o = (size_t)i * field_bytes;
+  sim_facets g;
+  g.disp_x = (char*)f.disp_x + o;
+  g.disp_y = (char*)f.disp_y + o;
+  g.h = (char*)f.h + o;
+  g.sx = (char*)f.sx + o;
+  g.sy = (char*)f.sy + o;
+  g.jac = (char*)f.jac + o;
+  g.ddisp_x = (char*)f.ddisp_x + o;
+  g.ddisp_y = (char*)f.ddisp_y + o;
+  g.dh = (char*)f.dh + o;
+  return g;
+}
+
+bool times_ok(const double* times, int32_t count) {
+  if (!times) return false;
+  for (int32_t i = 0; i < count; ++i)
+    if (!isfin(times[i])) return false;
+  return true;
+}
+
 bool facets_ok(const sim_facets* f) {
   if (!f) return false;
   void* const p[9] = {f->disp_x, f->disp_y, f->h, f->sx, f->sy, f->jac, f->ddisp_x, f->ddisp_y,
@@ -836,47 +899,36 @@ sim_status sim_run_updates(sim_ctx* ctx, const sim_grid* grid, const void* prepa
   if (s != SIM_OK) return s;
   if (!prepared || !t_fast || !times) return SIM_ERR_ARG;
   if (count < 1 || j0 < 0 || n_spec < 1 || j0 > n_spec - count) return SIM_ERR_SHAPE;
-  for (int32_t i = 0; i < count; ++i)
-    if (!isfin(times[i])) return SIM_ERR_ARG;
-  const int NL = count > 1 ? std::min(ctx->lanes, (int)count) : 1;
-  if (NL == 1) {
-    for (int32_t i = 0; i < count && s == SIM_OK; ++i)
-      s = update_and_accumulate_impl(ctx, grid, prepared, true, radar, times[i], j0 + i, t_fast,
-                                     n_spec, counters, nullptr, stream);
-    return s;
-  }
-  // Lanes: update j0 + i runs on lane i mod NL (lane 0 the caller's stream)
-  // with that lane's workspace slice; the lanes are forked from the caller's
-  // stream and joined back to it, so the call is ordered on `stream` like
-  // the loop above (also under graph capture).  Updates write distinct
-  // spectra; the counters are added atomically.
-  const size_t slice = align256(L.total);
-  if (ctx->ws_bytes < (size_t)ctx->lanes * slice) return SIM_ERR_WORKSPACE;
-  s = use_device(ctx);
+  if (!times_ok(times, count)) return SIM_ERR_ARG;
+  // update j0 + i on lane i mod lanes with that lane's workspace slice;
+  // updates write distinct spectra, the counters are added atomically
+  return run_on_lanes(ctx, count, align256(L.total), (hipStream_t)stream,
+                      [&](int32_t i, hipStream_t ls) {
+                        return update_and_accumulate_impl(ctx, grid, prepared, true, radar,
+                                                          times[i], j0 + i, t_fast, n_spec,
+                                                          counters, nullptr, ls);
+                      });
+}
+
+sim_status sim_range_doppler_accumulate_run(sim_ctx* ctx, const sim_grid* grid,
+                                            const sim_facets* facets, const sim_radar* radar,
+                                            int32_t j0, int32_t count, const double* times,
+                                            void* t_fast, int32_t n_spec,
+                                            sim_counters* counters, void* stream) {
+  WsLayout L;
+  sim_status s = common_checks(ctx, grid, radar, &L);
   if (s != SIM_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  s = dev(hipEventRecord(ctx->lane_ev[0], st));
-  for (int l = 1; l < NL && s == SIM_OK; ++l)
-    s = dev(hipStreamWaitEvent(ctx->lane_st[l - 1], ctx->lane_ev[0], 0));
-  if (s != SIM_OK) return s;
-  void* const ws0 = ctx->ws;
-  const size_t ws_bytes0 = ctx->ws_bytes;
-  ctx->ws_bytes = slice;
-  for (int32_t i = 0; i < count && s == SIM_OK; ++i) {
-    const int l = i % NL;
-    ctx->ws = (char*)ws0 + (size_t)l * slice;
-    s = update_and_accumulate_impl(ctx, grid, prepared, true, radar, times[i], j0 + i, t_fast,
-                                   n_spec, counters, nullptr, l ? ctx->lane_st[l - 1] : st);
-  }
-  ctx->ws = ws0;
-  ctx->ws_bytes = ws_bytes0;
-  // always join, so that a capture stays well formed
-  for (int l = 1; l < NL; ++l) {
-    sim_status sj = dev(hipEventRecord(ctx->lane_ev[l], ctx->lane_st[l - 1]));
-    if (sj == SIM_OK) sj = dev(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
-    if (sj != SIM_OK && s == SIM_OK) s = sj;
-  }
-  return s;
+  if (!facets_ok(facets) || !t_fast || !times) return SIM_ERR_ARG;
+  if (count < 1 || j0 < 0 || n_spec < 1 || j0 > n_spec - count) return SIM_ERR_SHAPE;
+  if (!times_ok(times, count)) return SIM_ERR_ARG;
+  const size_t field = (size_t)grid->nx * grid->ny * (csize(ctx) / 2);
+  return run_on_lanes(ctx, count, align256(L.total), (hipStream_t)stream,
+                      [&](int32_t i, hipStream_t ls) {
+                        const sim_facets fi = stacked_facets(*facets, i, field);
+                        return sim_range_doppler_accumulate(ctx, grid, &fi, radar, times[i],
+                                                            j0 + i, t_fast, n_spec, counters,
+                                                            nullptr, ls);
+                      });
 }
 
 sim_status sim_segments_to_iq(sim_ctx* ctx, const sim_radar* radar, const void* t_fast,
@@ -999,6 +1051,34 @@ sim_status sim_range_doppler_accumulate_adjoint(sim_ctx* ctx, const sim_grid* gr
     return dev(simk::launch_accumulate_adjoint<double>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy,
                                                        st));
   return dev(simk::launch_accumulate_adjoint<float>(fp, gp, rp, Tj, grad_h, grad_sx, grad_sy, st));
+}
+
+sim_status sim_range_doppler_accumulate_adjoint_run(sim_ctx* ctx, const sim_grid* grid,
+                                                    const sim_facets* facets,
+                                                    const sim_radar* radar, int32_t j0,
+                                                    int32_t count, const double* times,
+                                                    const void* t_fast_bar, int32_t n_spec,
+                                                    void* grad_h, void* grad_sx, void* grad_sy,
+                                                    void* stream) {
+  if (ctx && ctx->tab_slot >= 0) return SIM_ERR_UNSUPPORTED;   // closed forms only
+  if (!ctx) return SIM_ERR_ARG;
+  sim_status s = check_grid(ctx, grid);
+  if (s != SIM_OK) return s;
+  s = check_radar(radar);
+  if (s != SIM_OK) return s;
+  if (!facets_ok(facets) || !t_fast_bar || !grad_h || !grad_sx || !grad_sy || !times)
+    return SIM_ERR_ARG;
+  if (count < 1 || j0 < 0 || n_spec < 1 || j0 > n_spec - count) return SIM_ERR_SHAPE;
+  if (!times_ok(times, count)) return SIM_ERR_ARG;
+  const size_t field = (size_t)grid->nx * grid->ny * (csize(ctx) / 2);
+  // a per-facet gather into distinct gradient slices: no workspace
+  return run_on_lanes(ctx, count, 0, (hipStream_t)stream, [&](int32_t i, hipStream_t ls) {
+    const sim_facets fi = stacked_facets(*facets, i, field);
+    const size_t o = (size_t)i * field;
+    return sim_range_doppler_accumulate_adjoint(ctx, grid, &fi, radar, times[i], j0 + i,
+                                                t_fast_bar, n_spec, (char*)grad_h + o,
+                                                (char*)grad_sx + o, (char*)grad_sy + o, ls);
+  });
 }
 
 sim_status sim_delay_doppler(sim_ctx* ctx, const sim_radar* radar, const void* y,

@@ -50,7 +50,8 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
             "sim_range_doppler_accumulate_noalloc", "sim_update_and_accumulate", "sim_prepared_spectrum_size", "sim_prepare_spectrum",
             "sim_update_and_accumulate_prepared", "sim_run_updates", "sim_segments_to_iq",
             "sim_waveform_loss", "sim_waveform_loss_adjoint", "sim_segments_to_iq_adjoint",
-            "sim_range_doppler_accumulate_adjoint",
+            "sim_range_doppler_accumulate_adjoint", "sim_range_doppler_accumulate_run",
+            "sim_range_doppler_accumulate_adjoint_run",
             "sim_batch_create", "sim_batch_destroy", "sim_batch_workspace_size",
             "sim_batch_run", "sim_set_tuning", "sim_delay_doppler", "sim_set_tables",
             "sim_streamer_create", "sim_streamer_destroy", "sim_streamer_cache_size",
@@ -156,6 +157,16 @@ _sig = {
                                                             ctypes.POINTER(sim_facets),
                                                             ctypes.POINTER(sim_radar), _D, _I,
                                                             _P, _I, _P, _P, _P, _P]),
+    "sim_range_doppler_accumulate_run": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid),
+                                                        ctypes.POINTER(sim_facets),
+                                                        ctypes.POINTER(sim_radar), _I, _I,
+                                                        ctypes.POINTER(ctypes.c_double), _P, _I,
+                                                        _P, _P]),
+    "sim_range_doppler_accumulate_adjoint_run": (ctypes.c_int, [_P, ctypes.POINTER(sim_grid),
+                                                                ctypes.POINTER(sim_facets),
+                                                                ctypes.POINTER(sim_radar), _I, _I,
+                                                                ctypes.POINTER(ctypes.c_double),
+                                                                _P, _I, _P, _P, _P, _P]),
     "sim_batch_create": (ctypes.c_int, [_P, _I, ctypes.POINTER(sim_grid),
                                         ctypes.POINTER(sim_radar), ctypes.POINTER(_I),
                                         ctypes.POINTER(_P)]),
@@ -310,6 +321,28 @@ def sim_segments_to_iq_adjoint(ctx, radar, y_bar_ptr, n_spec, t_bar_ptr, stream)
     _check("sim_segments_to_iq_adjoint",
            _lib.sim_segments_to_iq_adjoint(ctx, ctypes.byref(radar), y_bar_ptr, n_spec, t_bar_ptr,
                                            stream))
+
+
+def _times(times):
+    return (ctypes.c_double * len(times))(*[float(x) for x in times])
+
+
+def sim_range_doppler_accumulate_run(ctx, grid, facets, radar, j0, times, t_fast_ptr, n_spec,
+                                     counters_ptr, stream) -> None:
+    _check("sim_range_doppler_accumulate_run",
+           _lib.sim_range_doppler_accumulate_run(ctx, ctypes.byref(grid), ctypes.byref(facets),
+                                                 ctypes.byref(radar), j0, len(times),
+                                                 _times(times), t_fast_ptr, n_spec, counters_ptr,
+                                                 stream))
+
+
+def sim_range_doppler_accumulate_adjoint_run(ctx, grid, facets, radar, j0, times, t_bar_ptr,
+                                             n_spec, gh_ptr, gsx_ptr, gsy_ptr, stream) -> None:
+    _check("sim_range_doppler_accumulate_adjoint_run",
+           _lib.sim_range_doppler_accumulate_adjoint_run(ctx, ctypes.byref(grid),
+                                                         ctypes.byref(facets), ctypes.byref(radar),
+                                                         j0, len(times), _times(times), t_bar_ptr,
+                                                         n_spec, gh_ptr, gsx_ptr, gsy_ptr, stream))
 
 
 def sim_range_doppler_accumulate_adjoint(ctx, grid, facets, radar, t, j, t_bar_ptr, n_spec,
@@ -492,9 +525,12 @@ class Simulator:
         return {n: self.torch.empty((g.ny, g.nx), dtype=self.real_dtype, device=self.device)
                 for n in FACET_FIELDS}
 
-    def _facets_struct(self, fac):
+    def _facets_struct(self, fac, count=None):
+        """sim_facets of a facet set ([ny][nx] fields) or, with count, of a
+        stacked run ([count][ny][nx] fields)."""
         g = self.grid
-        ptrs = [self._need(fac[n], self.real_dtype, (g.ny, g.nx), n) for n in FACET_FIELDS]
+        shape = (g.ny, g.nx) if count is None else (count, g.ny, g.nx)
+        ptrs = [self._need(fac[n], self.real_dtype, shape, n) for n in FACET_FIELDS]
         return sim_facets(*ptrs)
 
     def empty_spectra(self, n_spec):
@@ -674,6 +710,34 @@ class Simulator:
             self._need(y_bar, self.complex_dtype, ((n_spec - 1) * r.n_fast, r.n_gates), "y_bar"),
             n_spec, tb.data_ptr(), self._stream(stream))
         return tb
+
+    def range_doppler_accumulate_run(self, facets, times, j0, t_fast, counters=None, stream=None):
+        """range_doppler_accumulate of updates j0 .. j0 + len(times) - 1 in one
+        call; every field of `facets` is [len(times)][ny][nx]."""
+        n_spec = t_fast.shape[0]
+        r = self.radar
+        sim_range_doppler_accumulate_run(
+            self.ctx, self.grid, self._facets_struct(facets, len(times)), self.radar, int(j0),
+            times,
+            self._need(t_fast, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_fast"),
+            n_spec,
+            None if counters is None else self._need(counters, self.torch.int64, (6,), "counters"),
+            self._stream(stream))
+
+    def range_doppler_accumulate_adjoint_run(self, facets, times, j0, t_bar, out, stream=None):
+        """range_doppler_accumulate_adjoint of updates j0 .. j0 + len(times) - 1
+        in one call; the fields of `facets` and the three gradients of `out`
+        (h, sx, sy) are [len(times)][ny][nx]."""
+        g = self.grid
+        r = self.radar
+        n_spec = t_bar.shape[0]
+        count = len(times)
+        ptrs = [self._need(o, self.real_dtype, (count, g.ny, g.nx), "gradient") for o in out]
+        sim_range_doppler_accumulate_adjoint_run(
+            self.ctx, self.grid, self._facets_struct(facets, count), self.radar, int(j0), times,
+            self._need(t_bar, self.complex_dtype, (n_spec, r.n_gates, r.n_doppler), "t_bar"),
+            n_spec, ptrs[0], ptrs[1], ptrs[2], self._stream(stream))
+        return {"h": out[0], "sx": out[1], "sy": out[2]}
 
     def range_doppler_accumulate_adjoint(self, facets, t, j, t_bar, out=None, stream=None):
         g = self.grid

@@ -41,3 +41,9 @@ def test_sample_times_spread_over_the_run():
     assert len(s) == 24 and s[0] == t[0] and s[-1] == t[-1]
     assert all(b > a for a, b in zip(s, s[1:]))
     assert at.sample_times(t[:10], 24) == t[:10]
+
+
+def test_lanes_margin_of_whole_steps():
+    t = {1: 2.942, 2: 2.779, 3: 2.715, 4: 2.739}
+    assert at.pick_lanes(t) == 2                     # the short-run margin
+    assert at.pick_lanes(t, margin=0.01) == 3
