@@ -49,7 +49,7 @@ LAYOUT_SHARE = {"surface_colpass": 8 + 32, "surface_rowpass": 32, "fused_rowpass
 # they were taken on.
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
-    "source_sha": "75579d9f68437a3e",
+    "source_sha": "8f63f3bf2156d9cf",
     "fp32": {"surface_colpass": 817e6, "surface_rowpass": 1141e6,
              "accumulate_facets": 607e6, "reduce_partials": 3e6},
     "fp64": {"surface_colpass": 1347e6, "surface_rowpass": 2283e6,
