@@ -223,9 +223,8 @@ def run_delay_doppler(sim, Y, torch, burst=64, reps=20):
     burst, range migration corrected, multi-look) of the step's IQ: time per
     call (HIP events on the launch stream), the HBM bytes it must move (the
     IQ read twice, the beams written and read back by the range pass and read
-    by the multi-look) and the waveform against the oracle on the same IQ."""
-    import numpy as np
-    import oracle.delay_doppler as odd
+    by the multi-look).  Its agreement with the oracle is the tests' business
+    (the oracle runs here only in the CPU-baseline leg)."""
     st = torch.cuda.current_stream()
     out = sim.delay_doppler(Y, burst=burst)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -238,18 +237,9 @@ def run_delay_doppler(sim, Y, torch, burst=64, reps=20):
     nb = Y.shape[0] // burst
     cs = Y.element_size()
     moved = 2 * Y.numel() * cs + 4 * nb * burst * Y.shape[1] * cs
-    _, w_ref = odd.delay_doppler(Y.cpu().numpy().astype(np.complex128), sim_radar_view(sim),
-                                 burst=burst, centroid=None, migration=True)
-    err = float(np.linalg.norm(out["waveform"].cpu().numpy() - w_ref) / np.linalg.norm(w_ref))
     return {"burst": burst, "bursts": nb, "ms_per_call": round(s * 1e3, 4),
             "bytes_per_call": moved, "achieved_gbs": round(moved / s / 1e9, 1),
-            "waveform_rel_l2_vs_oracle": err}
-
-
-def sim_radar_view(sim):
-    """The context's radar as the oracle reads it (attribute access)."""
-    r = sim.radar
-    return type("Radar", (), {k: getattr(r, k) for k, _ in r._fields_})()
+            "waveform_finite": bool(torch.isfinite(out["waveform"]).all().item())}
 
 
 def run_batch(a, members, steps, warmup, torch):

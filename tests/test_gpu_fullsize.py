@@ -33,7 +33,16 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 CASES = [("track_4096", "fp32"), ("track_4096", "fp64"), ("gradient_2048", "fp32"),
-         ("stress_8192x16384", "fp32")]
+         ("stress_8192x16384", "fp32"), ("batch_8192", "fp32"), ("batch_8192", "fp64")]
+
+
+def _workload(which):
+    """A named workload; batch_8192 is the first 8192^2 member of the
+    16-realisation batch (8192 rows: two-column plane tiles, a layout of its
+    own between the 4096^2 track and the 16384-row stress grid)."""
+    if which == "batch_8192":
+        return next(w for w in workloads.batched_16() if w.grid.nx == 8192)
+    return workloads.ALL[which]()
 RUN_CASES = [("stress_8192x16384", "fp32"), ("track_4096", "fp32"), ("track_4096", "fp64")]
 
 
@@ -62,7 +71,7 @@ def _row_grid(grid, iy):
 def test_full_size_update_matches_oracle_samples(which, prec):
     from paper_2408_11472_amd import simradar
     print_case("fullsize", which, prec)
-    wl = workloads.ALL[which]()
+    wl = _workload(which)
     g, r = wl.grid, wl.radar
     fp64 = prec == "fp64"
     pcode = simradar.SIM_PREC_FP64 if fp64 else simradar.SIM_PREC_FP32_PHASE64
