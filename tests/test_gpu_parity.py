@@ -156,7 +156,8 @@ def test_accumulate_adds_and_repeats(prec, pcode, npdt):
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
 @pytest.mark.parametrize("nx,ny,cwm", [(16, 16, 1), (64, 32, 1), (32, 128, 0), (256, 256, 1),
-                                       (1024, 64, 1), (8192, 32, 1), (32, 16384, 1)])
+                                       (1024, 64, 1), (4096, 64, 0), (8192, 32, 1),
+                                       (32, 16384, 1)])
 def test_surface_update_matches_oracle(prec, pcode, npdt, nx, ny, cwm):
     if prec == "fp64" and ny > 8192:
         pytest.skip("ny > 8192 is float-only (LDS of one column)")
@@ -300,8 +301,8 @@ def test_full_run_small_256(prec, pcode, npdt):
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
-@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (256, 256), (8192, 32), (32, 16384),
-                                   (1024, 64)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (256, 256), (4096, 64), (8192, 32),
+                                   (32, 16384), (1024, 64)])
 def test_prepared_spectrum_gives_the_same_update(prec, pcode, npdt, nx, ny):
     """The column pass reading the prepared spectrum computes exactly what it
     computes from the FFT-order spectrum."""
