@@ -486,6 +486,7 @@ def main():
             "value": round(s32["facet_updates_per_s"], 1), "unit": "facet-updates/s",
             "iq_pulses_per_s": round(s32["iq_pulses_per_s"], 1),
             "kernels_ms_per_step": s32["kernels_ms_per_step"],
+            "tuning": s32["tuning"],
             "roofline": {k: v for k, v in s32["roofline"].items() if k != "traffic"}}
         line["batched_16"] = run_batch(a, workloads.batched_16(), max(2, a.extra_steps), 1, torch)
         line["nfast_sweep"] = run_nfast_sweep(torch, tune=not a.no_autotune)
