@@ -35,7 +35,11 @@
  *  - Grid sides are powers of two: 16 <= nx <= 8192, 16 <= ny <= 16384
  *    (ny <= 8192 in FP64).
  *    Doppler bins n_doppler: power of two, 2 <= n_doppler <= 2048.
- *  - Calls that run concurrently on one context race on its workspace.
+ *  - A context serves one host thread at a time: calls that run concurrently
+ *    on one context race on its workspace, and a run call (sim_run_updates
+ *    and the accumulate run calls) also uses the context's lane streams and
+ *    events.  Work queued on different streams of one context by successive
+ *    calls must not overlap either (one workspace).
  */
 #ifndef SIMRADAR_H
 #define SIMRADAR_H
