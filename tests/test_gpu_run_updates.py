@@ -104,13 +104,21 @@ def _lane_case(prec, nx=128, ny=64):
     return sim, prep, times, wl
 
 
+@pytest.mark.parametrize("path", ["split", "fused"])
 @pytest.mark.parametrize("lanes", [2, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_run_updates_on_lanes_equals_one_lane(prec, lanes):
-    """Updates dealt to several streams, each with its own workspace slice:
-    the same spectra and counters as on the caller's stream alone."""
-    print_case("run_updates lanes", prec, lanes)
+def test_run_updates_on_lanes_equals_one_lane(prec, lanes, path):
+    """Updates dealt to several streams, each with its own workspace slice
+    (facet SoA on the split row path, band windows on both): the same spectra
+    and counters as on the caller's stream alone."""
+    from paper_2408_11472_amd import simradar
+    print_case("run_updates lanes", prec, lanes, path)
     sim, prep, times, wl = _lane_case(prec)
+    if path == "fused":
+        sim.set_row_path(simradar.SIM_ROW_PATH_FUSED)
+        sim.set_row_bands(16)
+    else:
+        sim.set_row_path(simradar.SIM_ROW_PATH_SPLIT)
     T1, c1 = sim.empty_spectra(wl.n_spec), sim.counters()
     sim.run_updates(prep, times, 0, T1, counters=c1)
     torch.cuda.synchronize()
