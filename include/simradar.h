@@ -35,6 +35,10 @@
  *  - Grid sides are powers of two: 16 <= nx <= 8192, 16 <= ny <= 16384
  *    (ny <= 8192 in FP64).
  *    Doppler bins n_doppler: power of two, 2 <= n_doppler <= 2048.
+ *    Range gates: 1 <= n_gates <= 65536; the calls that scatter facets into
+ *    spectra keep one Doppler bin of all gates in a 32 KiB LDS window, so
+ *    for them (and for sim_workspace_size) n_gates <= 4096 (FP32 + FP64
+ *    phase) or 2048 (FP64), else SIM_ERR_UNSUPPORTED before any launch.
  *  - A context serves one host thread at a time: calls that run concurrently
  *    on one context race on its workspace, and a run call (sim_run_updates
  *    and the accumulate run calls) also uses the context's lane streams and

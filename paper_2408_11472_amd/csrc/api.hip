@@ -456,6 +456,10 @@ sim_status common_checks(sim_ctx* c, const sim_grid* g, const sim_radar* r, WsLa
   if (r) {
     s = check_radar(r);
     if (s != SIM_OK) return s;
+    // the calls given a radar scatter facets, keeping one Doppler bin of all
+    // gates in an LDS window: a size that cannot is unsupported, whatever
+    // the workspace
+    if (window_bins(r->n_gates, r->n_doppler, csize(c), 0) < 1) return SIM_ERR_UNSUPPORTED;
   }
   if (!c->ws) return SIM_ERR_WORKSPACE;
   if (r) {

@@ -48,7 +48,8 @@ def _spec(wl):
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
 @pytest.mark.parametrize("G,N,n_fast,n_spec,window", [
     (5, 8, 8, 3, 0), (64, 64, 64, 9, 1), (128, 256, 256, 4, 0), (3, 16, 24, 4, 0),
-    (7, 64, 16, 5, 1), (1, 2, 1, 6, 0), (130, 512, 128, 3, 0)])
+    (7, 64, 16, 5, 1), (1, 2, 1, 6, 0), (130, 512, 128, 3, 0), (4, 2048, 512, 3, 1),
+    (2, 2048, 2048, 2, 0)])
 def test_segments_to_iq_matches_oracle(prec, pcode, npdt, G, N, n_fast, n_spec, window):
     simradar = _sim()
     print_case("segments_to_iq", prec, G, N, n_fast, n_spec, window)
@@ -132,6 +133,68 @@ def test_accumulate_wide_doppler_windows_and_drop_rules(prec, pcode, npdt):
     assert err <= (1e-12 if prec == "fp64" else 1e-5), err
     c = cnt.cpu().numpy()
     assert [int(x) for x in c[:5]] == [cnt_ref[n] for n in osc.COUNTER_NAMES]
+
+
+@pytest.mark.parametrize("prec,pcode,npdt", PRECS)
+@pytest.mark.parametrize("which", ["bins", "gates"])
+def test_accumulate_at_the_largest_sizes(prec, pcode, npdt, which):
+    """The largest Doppler-bin count (2048, facets over most of them) and the
+    largest gate count a band window holds (one bin of all gates in 32 KiB:
+    4096 gates in float, 2048 in double, so the windows are one bin wide).
+    Twice those gates are refused before any launch."""
+    simradar = _sim()
+    gmax = 4096 if prec == "fp32" else 2048
+    G, N = (128, 2048) if which == "bins" else (gmax, 16)
+    print_case("accumulate largest", prec, which, G, N)
+    nx, ny = 64, 64
+    grid = workloads.Grid(nx=nx, ny=ny, dx=1.0, dy=1.0, x_origin=-32.0, y_origin=-32.0)
+
+    def radar_of(n_gates, spacing):
+        r = workloads.Radar(n_gates=n_gates, n_doppler=N, n_fast=N)
+        r.sat_x, r.sat_y0 = 0.0, 0.0
+        r.gate_spacing = spacing
+        r.window_start = r.altitude - (n_gates / 2 + 0.5) * spacing
+        return r
+
+    radar = radar_of(G, 0.05 if which == "bins" else 0.002)
+    fac = inputs.random_facets(nx, ny, seed=11, height_rms=1.0, dz_rms=0.01, disp_rms=0.3)
+    fac_r = rounded_facets(fac, npdt)
+    t = 0.0071
+    T_ref, code_ref, cnt_ref = osc.accumulate(fac_r, grid, radar, t)
+    kept = code_ref[code_ref >= 0]
+    lg = N.bit_length() - 1
+    if which == "bins":
+        assert len(np.unique(kept & (N - 1))) > N // 2
+    else:
+        assert len(np.unique(kept >> lg)) > 256
+    sim = simradar.Simulator(grid, radar, pcode)
+    Tt = sim.empty_spectra(2)
+    cnt = sim.counters()
+    code = torch.empty((ny, nx), dtype=torch.int32, device="cuda")
+    ft = to_torch_facets(fac_r, sim.real_dtype, "cuda")
+    sim.range_doppler_accumulate(ft, t, 1, Tt, counters=cnt, facet_code=code)
+    torch.cuda.synchronize()
+    assert np.array_equal(code.cpu().numpy(), code_ref)
+    err = rel_l2(Tt.cpu().numpy()[1], T_ref)
+    assert err <= (1e-12 if prec == "fp64" else 1e-5), err
+    assert [int(x) for x in cnt.cpu().numpy()[:5]] == [cnt_ref[n] for n in osc.COUNTER_NAMES]
+    if which == "gates":
+        # twice the gates: no workspace size, and an accumulate call on this
+        # context with such a radar returns before any launch
+        with pytest.raises(simradar.SimError) as e:
+            simradar.Simulator(grid, radar_of(2 * gmax, 0.002), pcode)
+        assert e.value.status == simradar.SIM_ERR_UNSUPPORTED
+        rr = simradar.sim_radar.from_buffer_copy(sim.radar)
+        rr.n_gates = 2 * gmax
+        T2 = torch.zeros((2, 2 * gmax, N), dtype=sim.complex_dtype, device="cuda")
+        with pytest.raises(simradar.SimError) as e:
+            simradar.sim_range_doppler_accumulate(sim.ctx, sim.grid, sim._facets_struct(ft), rr,
+                                                  t, 1, T2.data_ptr(), 2, None, None,
+                                                  sim._stream(None))
+        assert e.value.status == simradar.SIM_ERR_UNSUPPORTED
+        torch.cuda.synchronize()
+        assert not T2.cpu().numpy().any()
+    sim.close()
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
