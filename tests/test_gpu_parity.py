@@ -198,6 +198,54 @@ def test_accumulate_at_the_largest_sizes(prec, pcode, npdt, which):
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
+@pytest.mark.parametrize("reason", ["window", "nonfinite", "folded"])
+def test_every_facet_dropped(prec, pcode, npdt, reason):
+    """Degenerate updates where no facet reaches a spectrum (all out of the
+    range window, all non-finite, all folded): the band windows stay empty,
+    the ordered reduce finds no slot, T_fast stays exactly zero and every
+    facet is counted once, as the oracle counts it; out of the window also
+    end to end from the spectrum on both row paths."""
+    simradar = _sim()
+    print_case("every facet dropped", prec, reason)
+    wl = workloads.tiny(nx=64, ny=32, spacing=1.5, n_gates=16, n_doppler=16, n_fast=16)
+    g, r = wl.grid, wl.radar
+    if reason == "window":
+        r.window_start = r.altitude + 1000.0          # every range is before the window
+    fac = inputs.random_facets(g.nx, g.ny, seed=3, height_rms=0.5, dz_rms=0.001,
+                               disp_rms=0.1)
+    if reason == "nonfinite":
+        fac["h"][:] = np.nan
+    elif reason == "folded":
+        fac["jac"][:] = -0.25
+    fac_r = rounded_facets(fac, npdt)
+    t = 0.004
+    T_ref, code_ref, cnt_ref = osc.accumulate(fac_r, g, r, t)
+    assert not np.any(T_ref) and cnt_ref["illuminated"] == 0
+    sim = simradar.Simulator(g, r, pcode)
+    T = sim.empty_spectra(2)
+    cnt = sim.counters()
+    code = torch.empty((g.ny, g.nx), dtype=torch.int32, device="cuda")
+    sim.range_doppler_accumulate(to_torch_facets(fac_r, sim.real_dtype, "cuda"), t, 1, T,
+                                 counters=cnt, facet_code=code)
+    torch.cuda.synchronize()
+    assert not T.cpu().numpy().any()
+    assert np.array_equal(code.cpu().numpy(), code_ref)
+    assert [int(x) for x in cnt.cpu().numpy()[:5]] == [cnt_ref[n] for n in osc.COUNTER_NAMES]
+    if reason == "window":
+        spec = torch.as_tensor(_spec(wl).astype(np.complex128 if prec == "fp64"
+                                                else np.complex64), device="cuda")
+        for path in (simradar.SIM_ROW_PATH_SPLIT, simradar.SIM_ROW_PATH_FUSED):
+            sim.set_row_path(path)
+            T2, c2 = sim.empty_spectra(2), sim.counters()
+            sim.update_and_accumulate(spec, t, 0, T2, counters=c2)
+            torch.cuda.synchronize()
+            assert not T2.cpu().numpy().any(), path
+            c2 = c2.cpu().numpy()
+            assert int(c2[0]) == 0 and int(c2[:5].sum()) == g.nx * g.ny, (path, c2)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,pcode,npdt", PRECS)
 def test_accumulate_adds_and_repeats(prec, pcode, npdt):
     # accumulate semantics: a second call adds the same spectrum again
     simradar = _sim()
