@@ -198,6 +198,39 @@ def test_accumulate_at_the_largest_sizes(prec, pcode, npdt, which):
 
 
 @pytest.mark.parametrize("prec,pcode,npdt", PRECS)
+@pytest.mark.parametrize("G", [1, 37, 130])
+def test_accumulate_gate_counts_not_powers_of_two(prec, pcode, npdt, G):
+    """Gate counts that are not powers of two (one gate, 37, 130): band
+    windows of G rows and one reduce block per gate, against the oracle."""
+    simradar = _sim()
+    print_case("accumulate gates", prec, G)
+    nx, ny, N = 64, 64, 64
+    grid = workloads.Grid(nx=nx, ny=ny, dx=1.0, dy=1.0, x_origin=-32.0, y_origin=-32.0)
+    radar = workloads.Radar(n_gates=G, n_doppler=N, n_fast=N)
+    radar.sat_x, radar.sat_y0 = 0.0, 0.0
+    radar.gate_spacing = 0.02
+    radar.window_start = radar.altitude - (G / 2 + 0.5) * radar.gate_spacing
+    fac = inputs.random_facets(nx, ny, seed=G, height_rms=0.5, dz_rms=0.002, disp_rms=0.2)
+    fac_r = rounded_facets(fac, npdt)
+    t = 0.0031
+    T_ref, code_ref, cnt_ref = osc.accumulate(fac_r, grid, radar, t)
+    assert cnt_ref["illuminated"] > 0 and cnt_ref["out_of_window"] > 0
+    sim = simradar.Simulator(grid, radar, pcode)
+    Tt = sim.empty_spectra(2)
+    cnt = sim.counters()
+    code = torch.empty((ny, nx), dtype=torch.int32, device="cuda")
+    sim.range_doppler_accumulate(to_torch_facets(fac_r, sim.real_dtype, "cuda"), t, 1, Tt,
+                                 counters=cnt, facet_code=code)
+    torch.cuda.synchronize()
+    assert np.array_equal(code.cpu().numpy(), code_ref)
+    err = rel_l2(Tt.cpu().numpy()[1], T_ref)
+    assert err <= (1e-12 if prec == "fp64" else 1e-5), err
+    assert not Tt.cpu().numpy()[0].any()
+    assert [int(x) for x in cnt.cpu().numpy()[:5]] == [cnt_ref[n] for n in osc.COUNTER_NAMES]
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,pcode,npdt", PRECS)
 @pytest.mark.parametrize("reason", ["window", "nonfinite", "folded"])
 def test_every_facet_dropped(prec, pcode, npdt, reason):
     """Degenerate updates where no facet reaches a spectrum (all out of the
