@@ -338,6 +338,10 @@ def run_single(a, wl, steps, warmup, torch, with_fp64=True, cpu=True):
                      "traffic_unit": "HBM bytes per update (rocprofv3 counters)",
                      "alg_bytes_per_update": ALG_BYTES_PER_FACET_UPDATE * scale * wl.n_facets,
                      "dominant_kernel": dominant_kernel(prof, wl, scale, measured_ok, name)})
+        # with several update lanes the launches of different updates overlap:
+        # a launch's duration then includes the time it shares the CUs
+        roof["dominant_kernel"].update({"update_lanes": sim.lanes,
+                                        "launches_overlap": sim.lanes > 1})
         dd = (run_delay_doppler(sim, Y, torch)
               if name == "fp32" and wl.name.startswith("track_4096") else None)
         # one more update with per-facet codes (outside the timed region)
