@@ -8,7 +8,8 @@ row pass + facet accumulate) using the library's HIP-event timing, keeps the
 fastest (the split path on a tie within FUSED_MARGIN); then it times a short
 run of updates (sim_run_updates) on 1 to 4 update lanes and keeps the
 fastest (fewer lanes on a tie within LANES_MARGIN).  The choice is cached in
-a JSON file keyed by the shape.  Cache: $SIMRADAR_TUNING_CACHE or
+a JSON file keyed by the shape and the library build (a rebuilt library is
+tuned again).  Cache: $SIMRADAR_TUNING_CACHE or
 ~/.cache/simradar/tuning.json.
 """
 from __future__ import annotations
@@ -39,13 +40,32 @@ def cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "simradar", "tuning.json")
 
 
+_BUILD_ID = None
+
+
+def library_build_id() -> str:
+    """First 12 hex digits of the SHA-256 of the loaded library file: choices
+    timed on one build of the kernels are not applied to another."""
+    global _BUILD_ID
+    if _BUILD_ID is None:
+        import hashlib
+        from . import simradar
+        h = hashlib.sha256()
+        with open(simradar.LIB_PATH, "rb") as f:
+            for chunk in iter(lambda: f.read(1 << 20), b""):
+                h.update(chunk)
+        _BUILD_ID = h.hexdigest()[:12]
+    return _BUILD_ID
+
+
 def shape_key(sim) -> str:
-    """Cache key of a shape: precision, grid sides, gates and bins.  The cache
-    file belongs to one machine (its path is per user or set by the caller);
-    the device name is left out because some runtimes (a profiler's) report
-    it empty."""
+    """Cache key of a shape: precision, grid sides, gates and bins, and the
+    library build.  The cache file belongs to one machine (its path is per
+    user or set by the caller); the device name is left out because some
+    runtimes (a profiler's) report it empty."""
     g, r = sim.grid, sim.radar
-    return f"prec{sim.precision}|{g.nx}x{g.ny}|G{r.n_gates}|N{r.n_doppler}"
+    return (f"prec{sim.precision}|{g.nx}x{g.ny}|G{r.n_gates}|N{r.n_doppler}"
+            f"|lib{library_build_id()}")
 
 
 def _load():

@@ -47,3 +47,17 @@ def test_lanes_margin_of_whole_steps():
     t = {1: 2.942, 2: 2.779, 3: 2.715, 4: 2.739}
     assert at.pick_lanes(t) == 2                     # the short-run margin
     assert at.pick_lanes(t, margin=0.01) == 3
+
+
+def test_cache_key_names_the_shape_and_the_library_build():
+    """A cached choice applies to one shape on one build of the library."""
+    import types
+    g = types.SimpleNamespace(nx=4096, ny=2048)
+    r = types.SimpleNamespace(n_gates=128, n_doppler=256)
+    sim = types.SimpleNamespace(grid=g, radar=r, precision=1)
+    key = at.shape_key(sim)
+    assert key.startswith("prec1|4096x2048|G128|N256|lib")
+    bid = at.library_build_id()
+    assert key.endswith(bid) and len(bid) == 12 and int(bid, 16) >= 0
+    sim.precision = 0
+    assert at.shape_key(sim) != key
