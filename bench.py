@@ -45,13 +45,14 @@ LAYOUT_SHARE = {"surface_colpass": 8 + 32, "surface_rowpass": 32, "fused_rowpass
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE (x2.000) and
 # WRITE_SIZE (x1.000), scaled by a 1 GiB copy in the same runs
-# (profiles/track_4096_hbm_counters.md), valid only for the kernel sources
-# they were taken on.
+# (profiles/track_4096_hbm_counters.md; the autotuned launch shapes of the
+# track: 256 accumulate bands in float, 512 in double), valid only for the
+# kernel sources they were taken on.
 KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "scatter.hpp", "launch.hpp")
 MEASURED = {
     "source_sha": "8f63f3bf2156d9cf",
-    "fp32": {"surface_colpass": 817e6, "surface_rowpass": 1141e6,
-             "accumulate_facets": 607e6, "reduce_partials": 3e6},
+    "fp32": {"surface_colpass": 812e6, "surface_rowpass": 1141e6,
+             "accumulate_facets": 606e6, "reduce_partials": 2e6},
     "fp64": {"surface_colpass": 1347e6, "surface_rowpass": 2283e6,
              "accumulate_facets": 1211e6, "reduce_partials": 3e6},
 }

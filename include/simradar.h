@@ -529,6 +529,9 @@ sim_status sim_streamer_run(sim_streamer *streamer, const sim_grid *grid, const 
                                   /*   size and set the workspace.  Short updates (small grids) */
                                   /*   then overlap; per-kernel times (sim_profile_*) of       */
                                   /*   overlapping launches include each other's share.        */
+#define SIM_TUNE_ACC_BANDS 3      /* most bands (blocks) of the facet accumulate: 0 = default   */
+                                  /*   (512), else a power of two from 64 to 512; fewer bands  */
+                                  /*   leave room on the CUs for other update lanes' kernels   */
 sim_status sim_set_tuning(sim_ctx *ctx, int key, int value);
 
 /* ---- per-kernel timing (profiling aid) ----------------------------------

@@ -7,7 +7,8 @@ number of LDS windows and row-pass blocks per update; or the split facet
 row pass + facet accumulate) using the library's HIP-event timing, keeps the
 fastest (the split path on a tie within FUSED_MARGIN); then it times a short
 run of updates (sim_run_updates) on 1 to 4 update lanes and keeps the
-fastest (fewer lanes on a tie within LANES_MARGIN).  The choice is cached in
+fastest (fewer lanes on a tie within LANES_MARGIN), and on more than one lane
+the band count of the facet accumulate (ACC_BANDS_MARGIN).  The choice is cached in
 a JSON file keyed by the shape and the library build (a rebuilt library is
 tuned again).  Cache: $SIMRADAR_TUNING_CACHE or
 ~/.cache/simradar/tuning.json.
@@ -31,6 +32,22 @@ CANDIDATE_LANES = (1, 2, 3, 4)
 # 6 % over the run; 8192 x 16384 stress 3 % in the tuner, 0.6 % slower over
 # the run of 513 updates), so the margin is set between the two.
 LANES_MARGIN = 0.04
+# Bands of the facet accumulate tried once more than one lane is kept: fewer
+# bands leave room on the CUs for the other lanes' kernels (measured on the
+# 4096^2 track, whole runs on 3 lanes: 46.8 ms with 256 bands against 48.3
+# with 512; on one lane 57.2 against 51.7), kept only when faster than the
+# default by more than ACC_BANDS_MARGIN on the same sampled run.
+CANDIDATE_ACC_BANDS = (512, 256)
+ACC_BANDS_MARGIN = 0.01
+# Runs of at most WHOLE_RUN_MAX updates (given their update times) are timed
+# whole for the lanes and the band count, since short samples misjudge both:
+# on the 4096^2 track (65 updates) a 24-update sample put 2 lanes within
+# LANES_MARGIN of 3 in one run (50.7 ms per step instead of 48.5) and showed
+# 0.8 % of the 3 % that 256 accumulate bands gain.  Whole runs there: 1 lane
+# 51.9 ms, 2 lanes 50.5, 3 lanes 48.6, 4 lanes 48.0; the margin for whole
+# runs keeps the choice away from those gaps (3 lanes).
+WHOLE_RUN_MAX = 128
+WHOLE_RUN_LANES_MARGIN = 0.025
 
 
 def cache_path() -> str:
@@ -89,6 +106,7 @@ def _apply(sim, entry):
     sim.set_row_path(entry["row_path"])
     sim.set_row_bands(entry["row_bands"])
     sim.set_update_lanes(entry.get("update_lanes", 1))
+    sim.set_acc_bands(entry.get("acc_bands", 0))
 
 
 def pick(times: dict) -> tuple:
@@ -100,6 +118,18 @@ def pick(times: dict) -> tuple:
     if best[0] == PATH_FUSED and split is not None and split <= times[best] * (1 + FUSED_MARGIN):
         return (PATH_SPLIT, 0)
     return best
+
+
+def pick_acc_bands(times: dict, margin: float = ACC_BANDS_MARGIN) -> int:
+    """The accumulate band setting from the run time of each band count
+    (512 the default): the fastest if it beats 512 by more than `margin`,
+    else 0 (the default)."""
+    if not times or 512 not in times:
+        return 0
+    best = min(times, key=times.get)
+    if best != 512 and times[best] < times[512] * (1 - margin):
+        return best
+    return 0
 
 
 def pick_lanes(times: dict, margin: float = LANES_MARGIN) -> int:
@@ -130,48 +160,82 @@ def sample_times(times, n: int) -> list:
     return [times[(i * (len(times) - 1)) // (n - 1)] for i in range(n)]
 
 
-def tune_lanes(sim, spec0, repeats: int = 3, times=None) -> dict:
-    """Time a run of updates on each candidate lane count (HIP events on the
-    launch stream, best of `repeats`); returns {lanes: ms}.  times: the
-    run's update times (sampled evenly); default: the first updates at
-    j n_fast / PRF."""
-    import torch
+def run_sample(sim, times):
+    """The update times a tuning run uses, and whether they are the whole
+    run: the run's own times when given and at most WHOLE_RUN_MAX, else
+    lane_run_updates of them sampled evenly (default: the first updates at
+    j n_fast / PRF)."""
     r = sim.radar
     n = lane_run_updates(sim)
     if times is None:
-        times = [(j * r.n_fast) / r.prf_hz for j in range(n)]
-    times = sample_times(times, n)
+        return [(j * r.n_fast) / r.prf_hz for j in range(n)], False
+    times = list(times)
+    if len(times) <= WHOLE_RUN_MAX:
+        return times, True
+    return sample_times(times, n), False
+
+
+def tune_lanes(sim, spec0, repeats: int = 3, times=None) -> dict:
+    """Time a run of updates on each candidate lane count (HIP events on the
+    launch stream, best of `repeats`); returns {lanes: ms}.  times: the
+    run's update times (run_sample)."""
+    times, _ = run_sample(sim, times)
     n = len(times)
     prep = sim.prepare_spectrum(spec0)
     T = sim.empty_spectra(n)
     out = {}
     for lanes in CANDIDATE_LANES:
         sim.set_update_lanes(lanes)
-        sim.run_updates(prep, times, 0, T)                   # warm-up
-        best = None
-        for _ in range(repeats):
-            st = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(st)
-            sim.run_updates(prep, times, 0, T)
-            e1.record(st)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        out[lanes] = best
+        out[lanes] = _time_run(sim, prep, times, T, repeats)
+    return out
+
+
+def _time_run(sim, prep, times, T, repeats):
+    """Best of `repeats` timed runs (after one warm-up), in ms."""
+    import torch
+    sim.run_updates(prep, times, 0, T)                       # warm-up
+    best = None
+    for _ in range(repeats):
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        sim.run_updates(prep, times, 0, T)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def tune_acc_bands(sim, spec0, repeats: int = 3, times=None) -> dict:
+    """Time a run (run_sample) on the simulator's current lanes with each
+    candidate accumulate band count; returns {bands: ms} ({} on one lane,
+    where the default is kept).  Leaves the default set."""
+    if sim.lanes <= 1:
+        return {}
+    times, _ = run_sample(sim, times)
+    prep = sim.prepare_spectrum(spec0)
+    T = sim.empty_spectra(len(times))
+    out = {}
+    for nb in CANDIDATE_ACC_BANDS:
+        sim.set_acc_bands(nb)
+        out[nb] = _time_run(sim, prep, times, T, repeats)
+    sim.set_acc_bands(0)
     return out
 
 
 def tune(sim, spec0, repeats: int = 6, use_cache: bool = True, run_times=None) -> dict:
     """Pick the row path and the band count of the fused row pass for this
     simulator's shape, then the update lanes (on the run's update times
-    `run_times` when given), and apply them.  Returns {"row_path": p, "row_bands": n,
-    "times_us": {...}, "update_lanes": l, "lanes_ms": {...}} (times per update
-    of every row path candidate, run times of every lane count)."""
+    `run_times` when given) and on more than one lane the accumulate band
+    count, and apply them.  Returns {"row_path": p, "row_bands": n,
+    "times_us": {...}, "update_lanes": l, "lanes_ms": {...}, "acc_bands": b,
+    "acc_bands_ms": {...}} (times per update of every row path candidate, run
+    times of every lane count and accumulate band count; b = 0: default)."""
     import torch
     key = shape_key(sim)
     cache = _load() if use_cache else {}
-    if key in cache and "row_path" in cache[key] and "update_lanes" in cache[key]:
+    if key in cache and all(k in cache[key] for k in ("row_path", "update_lanes", "acc_bands")):
         _apply(sim, cache[key])
         return cache[key]
     T = sim.empty_spectra(2)
@@ -194,12 +258,19 @@ def tune(sim, spec0, repeats: int = 6, use_cache: bool = True, run_times=None) -
     sim.set_row_path(best[0])
     sim.set_row_bands(best[1])
     lane_ms = tune_lanes(sim, spec0, times=run_times)
+    whole = run_sample(sim, run_times)[1]
+    lanes = pick_lanes(lane_ms, WHOLE_RUN_LANES_MARGIN if whole else LANES_MARGIN)
+    sim.set_update_lanes(lanes)
+    acc_ms = tune_acc_bands(sim, spec0, times=run_times)
     entry = {"row_path": best[0], "row_bands": best[1],
              "times_us": {("fused%d" % nb if p == PATH_FUSED else "split"): round(v, 1)
                           for (p, nb), v in times.items()},
-             "update_lanes": pick_lanes(lane_ms),
+             "update_lanes": lanes,
              "lanes_ms": {str(k): round(v, 3) for k, v in lane_ms.items()},
-             "lanes_updates": lane_run_updates(sim)}
+             "lanes_updates": len(run_sample(sim, run_times)[0]),
+             "lanes_whole_run": whole,
+             "acc_bands": pick_acc_bands(acc_ms),
+             "acc_bands_ms": {str(k): round(v, 3) for k, v in acc_ms.items()}}
     _apply(sim, entry)
     if use_cache:
         cache = _load()

@@ -29,6 +29,7 @@ struct sim_ctx {
   size_t ws_bytes;
   int row_bands;   // tuning: bands of the fused row pass (0 = default)
   int row_path;    // tuning: row path of the fused call (SIM_ROW_PATH_*)
+  int acc_bands;   // tuning: most bands of the facet accumulate (0 = default)
   bool capturing;  // a batch is being captured into a graph
   // per-kernel timing: a pool of event pairs made by sim_profile_enable, so
   // that no compute call creates events
@@ -553,7 +554,7 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
                              const sim_radar* r, double t, int32_t j, void* t_fast,
                              sim_counters* counters, int32_t* code, hipStream_t st,
                              const WsLayout& L, char* win_base = nullptr,
-                             int max_bands = kAccBands);
+                             int max_bands = 0);
 
 // Row path of the fused call: the fused row pass (facets never leave the
 // chip), or the facet row pass into the workspace followed by the facet
@@ -611,6 +612,7 @@ sim_status accumulate_facets(sim_ctx* c, const sim_grid* g, const sim_facets* f,
   const int wk = window_bins(r->n_gates, r->n_doppler, cs, 0);
   if (wk < 1) return SIM_ERR_UNSUPPORTED;
   const size_t P = (size_t)g->nx * g->ny;
+  if (max_bands <= 0) max_bands = c->acc_bands > 0 ? c->acc_bands : kAccBands;
   const int n_bands = acc_band_count(P, max_bands);
   const size_t band = acc_band_size(P, max_bands);
   const WinP wp = win_params(win_base ? win_base : (char*)c->ws, r, L, wk, n_bands, (int)band);
@@ -679,6 +681,7 @@ sim_status sim_create(sim_ctx** ctx, int device, sim_precision precision) {
   c->dropped = 0;
   c->row_bands = 0;
   c->row_path = SIM_ROW_PATH_AUTO;
+  c->acc_bands = 0;
   c->capturing = false;
   c->tab_slot = -1;
   c->lanes = 1;
@@ -1177,6 +1180,13 @@ sim_status sim_set_tuning(sim_ctx* ctx, int key, int value) {
     ctx->row_path = value;
     return SIM_OK;
   }
+  if (key == SIM_TUNE_ACC_BANDS) {
+    if (value < 0 || value > kAccBands || (value & (value - 1)) != 0 ||
+        (value > 0 && value < 64))
+      return SIM_ERR_ARG;
+    ctx->acc_bands = value;
+    return SIM_OK;
+  }
   if (key == SIM_TUNE_UPDATE_LANES) {
     if (value < 1 || value > kMaxUpdateLanes) return SIM_ERR_ARG;
     if (value == ctx->lanes) return SIM_OK;
@@ -1448,6 +1458,7 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
     lc.ws_bytes = b->lane_bytes[l];
     lc.row_bands = c->row_bands;
     lc.row_path = c->row_path;
+    lc.acc_bands = c->acc_bands;
     lc.capturing = c->capturing;
     lc.tab_slot = c->tab_slot;
     lc.lanes = 1;

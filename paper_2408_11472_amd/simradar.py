@@ -61,6 +61,7 @@ EXPORTED = ("sim_abi_version", "sim_status_string", "sim_create", "sim_destroy",
 SIM_TUNE_ROW_BANDS = 0
 SIM_TUNE_ROW_PATH = 1
 SIM_TUNE_UPDATE_LANES = 2
+SIM_TUNE_ACC_BANDS = 3
 SIM_ROW_PATH_AUTO, SIM_ROW_PATH_FUSED, SIM_ROW_PATH_SPLIT = 0, 1, 2
 
 KERNEL_KINDS = ("surface_colpass", "surface_rowpass", "fused_rowpass", "accumulate_facets",
@@ -650,6 +651,11 @@ class Simulator:
     def set_row_path(self, path: int):
         """Row path of update_and_accumulate: SIM_ROW_PATH_AUTO, _FUSED or _SPLIT."""
         sim_set_tuning(self.ctx, SIM_TUNE_ROW_PATH, int(path))
+
+    def set_acc_bands(self, n: int):
+        """Most bands (blocks) of the facet accumulate (0 = default 512, else a
+        power of two from 64 to 512)."""
+        sim_set_tuning(self.ctx, SIM_TUNE_ACC_BANDS, int(n))
 
     def set_update_lanes(self, lanes: int):
         """Streams run_updates deals the updates to (1 .. 4); the workspace is

@@ -61,3 +61,39 @@ def test_cache_key_names_the_shape_and_the_library_build():
     assert key.endswith(bid) and len(bid) == 12 and int(bid, 16) >= 0
     sim.precision = 0
     assert at.shape_key(sim) != key
+
+
+def test_accumulate_bands_kept_only_when_clearly_faster():
+    # measured on the 4096^2 track, 3 lanes: 256 bands 3 % faster -> kept
+    assert at.pick_acc_bands({512: 48.3, 256: 46.8}) == 256
+    # within the margin, or slower (one lane): the default (0)
+    assert at.pick_acc_bands({512: 48.3, 256: 47.9}) == 0
+    assert at.pick_acc_bands({512: 51.7, 256: 57.2}) == 0
+    assert at.pick_acc_bands({}) == 0                    # one lane: not timed
+    t = 100.0
+    assert at.pick_acc_bands({512: t, 256: t * (1 - at.ACC_BANDS_MARGIN) * 0.999}) == 256
+
+
+def test_short_runs_are_tuned_whole_long_ones_on_a_sample():
+    import types
+    g = types.SimpleNamespace(nx=4096, ny=4096)
+    r = types.SimpleNamespace(n_fast=256, prf_hz=17800.0)
+    sim = types.SimpleNamespace(grid=g, radar=r)
+    track = [j * 256 / 17800.0 for j in range(65)]
+    times, whole = at.run_sample(sim, track)
+    assert whole and times == track
+    long_run = [j * 128 / 17800.0 for j in range(513)]
+    times, whole = at.run_sample(sim, long_run)
+    assert not whole and len(times) == at.lane_run_updates(sim)
+    assert times[0] == long_run[0] and times[-1] == long_run[-1]
+    times, whole = at.run_sample(sim, None)
+    assert not whole and len(times) == at.lane_run_updates(sim)
+
+
+def test_whole_run_margin_keeps_three_lanes_on_the_track():
+    # whole runs of the 4096^2 track (65 updates): 3 lanes, away from the
+    # 1.2 % to 4 lanes and the 4 % to 2 lanes
+    whole = {1: 51.87, 2: 50.48, 3: 48.55, 4: 47.96}
+    assert at.pick_lanes(whole, at.WHOLE_RUN_LANES_MARGIN) == 3
+    assert at.pick_lanes({k: v * (1.003 if k == 3 else 1.0) for k, v in whole.items()},
+                         at.WHOLE_RUN_LANES_MARGIN) == 3
