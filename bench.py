@@ -569,20 +569,30 @@ def main_gradient(a, wl):
 
     # update lanes of the run calls (forward accumulate, adjoint): a few
     # whole steps on each lane count, the fewest within 1 % of the fastest
-    lanes_ms = {}
+    lanes_ms, bands_ms = {}, {}
+
+    def step_ms():
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 5 * 1e3
+
     if not a.no_autotune:
         from paper_2408_11472_amd import autotune
         for lanes in autotune.CANDIDATE_LANES:
             sim.set_update_lanes(lanes)
-            for _ in range(2):
-                step()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(5):
-                step()
-            torch.cuda.synchronize()
-            lanes_ms[lanes] = (time.perf_counter() - t0) / 5 * 1e3
+            lanes_ms[lanes] = step_ms()
         sim.set_update_lanes(autotune.pick_lanes(lanes_ms, margin=0.01))
+        # then the band count of the forward accumulate, on those lanes
+        if sim.lanes > 1:
+            for nb in autotune.CANDIDATE_ACC_BANDS:
+                sim.set_acc_bands(nb)
+                bands_ms[nb] = step_ms()
+            sim.set_acc_bands(autotune.pick_acc_bands(bands_ms))
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -603,6 +613,8 @@ def main_gradient(a, wl):
         "loss": float(L.detach()), "grad_h_finite": bool(torch.isfinite(gh).all().item()),
         "update_lanes": sim.lanes,
         "lanes_ms_per_step": {str(k): round(v, 3) for k, v in lanes_ms.items()} or None,
+        "acc_bands": autotune.pick_acc_bands(bands_ms) if bands_ms else 0,
+        "acc_bands_ms_per_step": {str(k): round(v, 3) for k, v in bands_ms.items()} or None,
     }
     print(json.dumps(line), flush=True)
     sim.close()
