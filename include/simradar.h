@@ -468,8 +468,8 @@ sim_status sim_batch_run(sim_batch *batch, void *const *spec0, void *const *t_fa
 #define SIM_BATCH_PERSISTENT 2
 sim_status sim_batch_set_mode(sim_batch *batch, int mode);
 
-/* Per-member tuning of the lanes mode (SIM_TUNE_ROW_PATH or
- * SIM_TUNE_ROW_BANDS, as sim_set_tuning): an autotuner sets each member the
+/* Per-member tuning of the lanes mode (SIM_TUNE_ROW_PATH, SIM_TUNE_ROW_BANDS
+ * or SIM_TUNE_ACC_BANDS, as sim_set_tuning): an autotuner sets each member the
  * values it found for that member's shape.  Members without their own value
  * use the context's.  The persistent mode always runs the split row path.
  * A graph captured by the batch is dropped (the next graph run captures

@@ -284,7 +284,9 @@ def tune_batch(batch, specs, T, Y=None, repeats: int = 2, shapes: bool = True) -
     the captured graph of each, and, with shapes=True, tune the row path of
     every member shape first (lanes mode runs each member through the
     context's row path; the persistent launches use the split path).
-    Returns {"mode": ..., "times_ms": {...}, "shapes": {...}}."""
+    The lanes mode is also timed with 256 accumulate bands for every member,
+    kept when it beats both modes by more than ACC_BANDS_MARGIN.  Returns
+    {"mode": ..., "acc_bands": b, "times_ms": {...}, "shapes": {...}}."""
     import time
 
     import torch
@@ -307,9 +309,17 @@ def tune_batch(batch, specs, T, Y=None, repeats: int = 2, shapes: bool = True) -
                                           e["row_path"])
             simradar.sim_batch_set_tuning(batch.batch, i, simradar.SIM_TUNE_ROW_BANDS,
                                           e["row_bands"])
+    def set_acc_bands(nb):
+        for i in range(len(batch.grids)):
+            simradar.sim_batch_set_tuning(batch.batch, i, simradar.SIM_TUNE_ACC_BANDS, nb)
+
     times = {}
-    for name, mode in (("lanes", simradar.SIM_BATCH_LANES),
-                       ("persistent", simradar.SIM_BATCH_PERSISTENT)):
+    # the lanes mode also with 256 accumulate bands for every member (members
+    # on different streams overlap, as update lanes do)
+    for name, mode, nb in (("lanes", simradar.SIM_BATCH_LANES, 0),
+                           ("persistent", simradar.SIM_BATCH_PERSISTENT, 0),
+                           ("lanes_acc256", simradar.SIM_BATCH_LANES, 256)):
+        set_acc_bands(nb)
         batch.set_mode(mode)
         batch.run(specs, T, Y, use_graph=True)            # capture + warm-up
         torch.cuda.synchronize()
@@ -318,7 +328,13 @@ def tune_batch(batch, specs, T, Y=None, repeats: int = 2, shapes: bool = True) -
             batch.run(specs, T, Y, use_graph=True)
         torch.cuda.synchronize()
         times[name] = (time.perf_counter() - t0) / repeats * 1e3
-    best = min(times, key=times.get)
-    batch.set_mode(simradar.SIM_BATCH_LANES if best == "lanes" else simradar.SIM_BATCH_PERSISTENT)
-    out.update({"mode": best, "times_ms": {k: round(v, 3) for k, v in times.items()}})
+    best = min(("lanes", "persistent"), key=times.get)
+    if times["lanes_acc256"] < times[best] * (1 - ACC_BANDS_MARGIN):
+        best = "lanes_acc256"
+    set_acc_bands(256 if best == "lanes_acc256" else 0)
+    batch.set_mode(simradar.SIM_BATCH_PERSISTENT if best == "persistent"
+                   else simradar.SIM_BATCH_LANES)
+    out.update({"mode": "lanes" if best == "lanes_acc256" else best,
+                "acc_bands": 256 if best == "lanes_acc256" else 0,
+                "times_ms": {k: round(v, 3) for k, v in times.items()}})
     return out

@@ -1300,7 +1300,7 @@ struct sim_batch {
   std::vector<int> desc_n;                    // active members of (update, class)
   std::vector<void*> desc_key;                // pointers the descriptors were built for
   int jmax;
-  std::vector<int> m_row_path, m_row_bands;   // per-member tuning (lanes mode)
+  std::vector<int> m_row_path, m_row_bands, m_acc_bands;   // per-member tuning (lanes mode)
 };
 
 namespace {
@@ -1473,6 +1473,7 @@ sim_status batch_enqueue(sim_batch* b, void* const* spec0, void* const* t_fast, 
         const double t = ((double)j * rr.n_fast) / rr.prf_hz;
         lc.row_path = b->m_row_path[r] >= 0 ? b->m_row_path[r] : c->row_path;
         lc.row_bands = b->m_row_bands[r] >= 0 ? b->m_row_bands[r] : c->row_bands;
+        lc.acc_bands = b->m_acc_bands[r] >= 0 ? b->m_acc_bands[r] : c->acc_bands;
         first = sim_update_and_accumulate_prepared(
             &lc, &b->grids[r], (char*)c->ws + b->prep_off[r], &rr, t, j, t_fast[r],
             b->updates[r] + 1, nullptr, nullptr, ls);
@@ -1561,6 +1562,7 @@ sim_status sim_batch_create(sim_ctx* ctx, int32_t n_real, const sim_grid* grids,
   b->mode = SIM_BATCH_PERSISTENT;
   b->m_row_path.assign(n_real, -1);
   b->m_row_bands.assign(n_real, -1);
+  b->m_acc_bands.assign(n_real, -1);
   b->jmax = 0;
   for (int r = 0; r < n_real; ++r) b->jmax = n_updates[r] > b->jmax ? n_updates[r] : b->jmax;
   for (int r = 0; r < n_real; ++r) {
@@ -1652,6 +1654,12 @@ sim_status sim_batch_set_tuning(sim_batch* b, int32_t member, int key, int value
   if (key == SIM_TUNE_ROW_BANDS) {
     if (value < 0 || value > kMaxBands || (value > 0 && !is_pow2(value))) return SIM_ERR_ARG;
     b->m_row_bands[member] = value;
+    return SIM_OK;
+  }
+  if (key == SIM_TUNE_ACC_BANDS) {
+    if (value < 0 || value > kAccBands || (value > 0 && (!is_pow2(value) || value < 64)))
+      return SIM_ERR_ARG;
+    b->m_acc_bands[member] = value;
     return SIM_OK;
   }
   return SIM_ERR_ARG;

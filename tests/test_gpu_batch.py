@@ -196,3 +196,35 @@ def test_persistent_mode_equals_lanes_mode_on_new_buffers(prec, pcode, cdt):
         batch.set_mode(7)
     batch.close()
 
+
+
+@pytest.mark.parametrize("prec,pcode,cdt", [("fp64", 0, np.complex128), ("fp32", 1, np.complex64)])
+def test_member_accumulate_bands_change_only_summation_order(prec, pcode, cdt):
+    """SIM_TUNE_ACC_BANDS per member of the lanes mode (a 512^2 member, where
+    64 bands and the default differ): the same spectra up to the order of the
+    window sums, eager and from a recaptured graph; bad values refused."""
+    from paper_2408_11472_amd import simradar
+    print_case("batch acc bands", prec)
+    wls = _members()[:2] + [workloads.tiny(nx=512, ny=512, spacing=2.0, n_gates=16,
+                                           n_doppler=16, n_fast=16, n_updates=2, seed=77)]
+    batch = simradar.Batch([(w.grid, w.radar, w.n_updates) for w in wls], pcode)
+    batch.set_mode(simradar.SIM_BATCH_LANES)
+    specs = [torch.as_tensor(_spec(w).astype(cdt), device="cuda") for w in wls]
+    T1, Y1 = batch.empty_outputs()
+    batch.run(specs, T1, Y1, use_graph=False)
+    lib = simradar._lib
+    for bad in (3, 32, 1024):
+        assert lib.sim_batch_set_tuning(batch.batch, 2, simradar.SIM_TUNE_ACC_BANDS, bad) == \
+            simradar.SIM_ERR_ARG
+    for i in range(len(wls)):
+        simradar.sim_batch_set_tuning(batch.batch, i, simradar.SIM_TUNE_ACC_BANDS, 64)
+    T2, Y2 = batch.empty_outputs()
+    batch.run(specs, T2, Y2, use_graph=False)
+    T3, Y3 = batch.empty_outputs()
+    batch.run(specs, T3, Y3, use_graph=True)
+    torch.cuda.synchronize()
+    tol = 1e-13 if prec == "fp64" else 1e-5
+    for a, b, c in zip(T1, T2, T3):
+        assert rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= tol
+        assert rel_l2(c.cpu().numpy(), a.cpu().numpy()) <= tol
+    batch.close()
